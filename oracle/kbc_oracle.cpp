@@ -1,0 +1,1034 @@
+// CPU FP64 oracle for the entropic multi-relaxation-time (KBC) lattice
+// Boltzmann step with Grad's-approximation walls and the stress-based wall
+// force, after Dorschner, Chikatamarla & Karlin, "Fluid-structure interaction
+// with the entropic lattice Boltzmann method".
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+// baseline leg of the benchmark load this library.  The product path never
+// links, imports or calls it, and it shares no source with the HIP library.
+//
+// Design: plain and slow on purpose.  Array-of-structures populations
+// f[node*Q + i]; separate passes for geometry, streaming, boundary filling and
+// collision; double precision throughout.  The shear / higher-order split uses
+// the generic inverse of the Q x Q monomial moment matrix, not a closed form.
+//
+// Parity status of each part is stated beside it:
+//   pinned          -- checked in tests against values fixed by the paper or
+//                      by mathematics (closed forms, invariants, brute force);
+//   parity unpinned -- only self-consistency and physical sanity checks exist
+//                      (Grad target values, fresh-node fill, stress
+//                      extrapolation to surface points).
+//
+// Lattice conventions: velocities c_i in {-1,0,1}^D with index
+// i = (cx+1) + 3(cy+1) + 9(cz+1), opposite direction Q-1-i, weights the tensor
+// product of the D1Q3 weights w(0)=2/3, w(+-1)=1/6 (speed of sound 1/sqrt(3)).
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Lattice (pinned: weight isotropy tests)
+// ---------------------------------------------------------------------------
+struct Lattice {
+  int D = 0, Q = 0, rest = 0;
+  int c[27][3] = {};
+  double w[27] = {};
+  int expo[27][3] = {};   // monomial exponents (p,q,r) of moment row k
+  double M[27][27] = {};  // monomial moment matrix M[k][i] = cx^p cy^q cz^r
+  double Minv[27][27] = {};
+};
+
+double w1d(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+
+// Gauss-Jordan inversion with partial pivoting of an n x n row-major matrix.
+bool invert(int n, const double* a, double* inv) {
+  std::vector<double> m(a, a + n * n);
+  for (int i = 0; i < n * n; ++i) inv[i] = 0.0;
+  for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(m[r * n + col]) > std::fabs(m[piv * n + col])) piv = r;
+    if (std::fabs(m[piv * n + col]) < 1e-14) return false;
+    if (piv != col)
+      for (int k = 0; k < n; ++k) {
+        std::swap(m[piv * n + k], m[col * n + k]);
+        std::swap(inv[piv * n + k], inv[col * n + k]);
+      }
+    const double p = m[col * n + col];
+    for (int k = 0; k < n; ++k) { m[col * n + k] /= p; inv[col * n + k] /= p; }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double f = m[r * n + col];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        m[r * n + k] -= f * m[col * n + k];
+        inv[r * n + k] -= f * inv[col * n + k];
+      }
+    }
+  }
+  return true;
+}
+
+double ipow(int c, int p) { double r = 1.0; for (int k = 0; k < p; ++k) r *= c; return r; }
+
+Lattice build_lattice(int Q) {
+  Lattice L;
+  L.Q = Q;
+  L.D = (Q == 9) ? 2 : 3;
+  L.rest = (Q - 1) / 2;
+  for (int i = 0; i < Q; ++i) {
+    L.c[i][0] = i % 3 - 1;
+    L.c[i][1] = (i / 3) % 3 - 1;
+    L.c[i][2] = (Q == 27) ? i / 9 - 1 : 0;
+    L.w[i] = w1d(L.c[i][0]) * w1d(L.c[i][1]) * (Q == 27 ? w1d(L.c[i][2]) : 1.0);
+    L.expo[i][0] = i % 3;
+    L.expo[i][1] = (i / 3) % 3;
+    L.expo[i][2] = (Q == 27) ? i / 9 : 0;
+  }
+  // Monomial ("natural") moment matrix M[k][i] = cx^p cy^q cz^r.
+  std::vector<double> M(Q * Q), Mi(Q * Q);
+  for (int k = 0; k < Q; ++k)
+    for (int i = 0; i < Q; ++i)
+      M[k * Q + i] = ipow(L.c[i][0], L.expo[k][0]) * ipow(L.c[i][1], L.expo[k][1]) *
+                     ipow(L.c[i][2], L.expo[k][2]);
+  invert(Q, M.data(), Mi.data());
+  for (int i = 0; i < Q; ++i)
+    for (int k = 0; k < Q; ++k) {
+      L.Minv[i][k] = Mi[i * Q + k];
+      L.M[i][k] = M[i * Q + k];
+    }
+  return L;
+}
+
+const Lattice& lattice(int Q) {
+  static const Lattice d2q9 = build_lattice(9);
+  static const Lattice d3q27 = build_lattice(27);
+  return Q == 9 ? d2q9 : d3q27;
+}
+
+// ---------------------------------------------------------------------------
+// Entropic equilibrium (Sec. II.A, Eqs. (4)-(5)); pinned: exact moments, the
+// Lagrange condition, and a numerical minimiser of H in the tests.
+// f^eq minimises H(f) = sum_i f_i ln(f_i/W_i) under mass and momentum.  For a
+// tensor-product lattice the Lagrange solution W_i exp(chi + zeta.c_i)
+// factorises per axis; solving the D1Q3 constraints of each axis gives
+//   f^eq_i = rho W_i prod_a (2 - s_a) x_a^{c_ia},
+//   s_a = sqrt(1 + 3 u_a^2),  x_a = (2 u_a + s_a) / (1 - u_a).
+// Requires rho > 0 and |u_a| < 1.
+// ---------------------------------------------------------------------------
+void equilibrium(const Lattice& L, double rho, const double* u, double* feq) {
+  double z[3], x[3];
+  for (int a = 0; a < 3; ++a) {
+    const double s = std::sqrt(1.0 + 3.0 * u[a] * u[a]);
+    z[a] = 2.0 - s;
+    x[a] = (2.0 * u[a] + s) / (1.0 - u[a]);
+  }
+  for (int i = 0; i < L.Q; ++i) {
+    double p = rho * L.w[i];
+    for (int a = 0; a < L.D; ++a) {
+      p *= z[a];
+      if (L.c[i][a] == 1) p *= x[a];
+      if (L.c[i][a] == -1) p /= x[a];
+    }
+    feq[i] = p;
+  }
+}
+
+void moments(const Lattice& L, const double* f, double* rho, double* u) {
+  double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < L.Q; ++i) {
+    r += f[i];
+    for (int a = 0; a < 3; ++a) j[a] += L.c[i][a] * f[i];
+  }
+  *rho = r;
+  for (int a = 0; a < 3; ++a) u[a] = j[a] / r;
+}
+
+// ---------------------------------------------------------------------------
+// Shear / higher-order split (Sec. II.A, Eqs. (2)-(3)); pinned: moment
+// identities and an independent closed form in the tests.
+// In the natural moment basis the populations decompose as f = k + s + h.  The
+// kinematic part k carries the conserved moments, so Delta k = 0.  The shear
+// part s carries the deviatoric (traceless) second-order moments; the trace of
+// the second-order moments goes to h unless trace_in_s is set.  Everything
+// else (third and fourth order) is h.  Delta s is obtained by taking the
+// monomial moments m = M Delta, keeping only the shear moments, and mapping
+// back with M^{-1}.
+// ---------------------------------------------------------------------------
+void split(const Lattice& L, const double* delta, int trace_in_s, double* ds, double* dh) {
+  const int Q = L.Q;
+  double m[27];
+  for (int k = 0; k < Q; ++k) {
+    double acc = 0.0;
+    for (int i = 0; i < Q; ++i) acc += L.M[k][i] * delta[i];
+    m[k] = acc;
+  }
+  // Trace of the second-order moments.
+  double trace = 0.0;
+  for (int k = 0; k < Q; ++k) {
+    const int p = L.expo[k][0], q = L.expo[k][1], r = L.expo[k][2];
+    if (p + q + r == 2 && (p == 2 || q == 2 || r == 2)) trace += m[k];
+  }
+  double ms[27];
+  for (int k = 0; k < Q; ++k) {
+    const int p = L.expo[k][0], q = L.expo[k][1], r = L.expo[k][2];
+    ms[k] = 0.0;
+    if (p + q + r != 2) continue;
+    const bool diag = (p == 2 || q == 2 || r == 2);
+    ms[k] = (diag && !trace_in_s) ? m[k] - trace / L.D : m[k];
+  }
+  for (int i = 0; i < Q; ++i) {
+    double acc = 0.0;
+    for (int k = 0; k < Q; ++k) acc += L.Minv[i][k] * ms[k];
+    ds[i] = acc;
+    dh[i] = delta[i] - acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// KBC collision at one node (Sec. II.A, Eqs. (1), (3), (6)); pinned:
+// conservation, LBGK limit, beta = 1/2 limit, gamma as the exact minimiser of
+// the quadratic entropy norm.
+//   f' = (1-beta) f + beta f^mirr = f - beta (2 Delta s + gamma Delta h)
+//   gamma = 1/beta - (2 - 1/beta) <Ds|Dh> / <Dh|Dh>,  <X|Y> = sum X_i Y_i / f^eq_i.
+// <Dh|Dh> = 0 gives gamma = 2 (the 0/0 case is not addressed by the paper).
+// collision == 1 forces gamma = 2 (LBGK with relaxation 2 beta).
+// Returns 0 on success, 1 if the node state is invalid (rho <= 0, |u_a| >= 1,
+// or not finite), in which case fout = f.
+// ---------------------------------------------------------------------------
+int collide(const Lattice& L, double beta, int collision, int trace_in_s, const double* f,
+            double* fout, double* gamma_out, double* feq_out = nullptr) {
+  const int Q = L.Q;
+  double rho, u[3];
+  moments(L, f, &rho, u);
+  bool ok = std::isfinite(rho) && rho > 0.0;
+  for (int a = 0; a < 3; ++a) ok = ok && std::isfinite(u[a]) && std::fabs(u[a]) < 1.0;
+  if (!ok) {
+    for (int i = 0; i < Q; ++i) fout[i] = f[i];
+    if (gamma_out) *gamma_out = 2.0;
+    return 1;
+  }
+  double feq[27], delta[27], ds[27], dh[27];
+  equilibrium(L, rho, u, feq);
+  for (int i = 0; i < Q; ++i) delta[i] = f[i] - feq[i];
+  split(L, delta, trace_in_s, ds, dh);
+  double gamma = 2.0;
+  if (collision == 0) {
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < Q; ++i) {
+      a += ds[i] * dh[i] / feq[i];
+      b += dh[i] * dh[i] / feq[i];
+    }
+    if (b != 0.0) gamma = 1.0 / beta - (2.0 - 1.0 / beta) * a / b;
+  }
+  for (int i = 0; i < Q; ++i) fout[i] = f[i] - beta * (2.0 * ds[i] + gamma * dh[i]);
+  if (gamma_out) *gamma_out = gamma;
+  if (feq_out)
+    for (int i = 0; i < Q; ++i) feq_out[i] = feq[i];
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Grad's approximation (Sec. II.C.1); pinned: reproduces rho, rho v and Pi.
+//   f*_i = W_i [ rho + (rho / cs^2) c_i.v + (1/(2 cs^4)) (Pi - rho cs^2 I):(c_i c_i - cs^2 I) ]
+// with cs^2 = 1/3.  Pi is a full 3x3 row-major tensor (2D uses the xy block).
+// ---------------------------------------------------------------------------
+void grad_fstar(const Lattice& L, double rho, const double* v, const double* Pi, double* out) {
+  const double cs2 = 1.0 / 3.0;
+  for (int i = 0; i < L.Q; ++i) {
+    double cv = 0.0, contr = 0.0;
+    for (int a = 0; a < L.D; ++a) {
+      cv += L.c[i][a] * v[a];
+      for (int b = 0; b < L.D; ++b) {
+        const double dab = (a == b) ? 1.0 : 0.0;
+        contr += (Pi[3 * a + b] - rho * cs2 * dab) * (L.c[i][a] * L.c[i][b] - cs2 * dab);
+      }
+    }
+    out[i] = L.w[i] * (rho + rho * cv / cs2 + contr / (2.0 * cs2 * cs2));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fluid stress (Sec. II.C.2): sigma = -p I - (1 - beta) Pi^(1), p = rho cs^2,
+// Pi^(1) = sum_i (f_i - f^eq_i) c_i c_i.  Pinned: rest fluid gives -p I, and
+// the Couette wall shear in the tests.  Output: row-major 3x3.
+// ---------------------------------------------------------------------------
+void stress(const Lattice& L, double beta, const double* f, double* sigma) {
+  double rho, u[3], feq[27];
+  moments(L, f, &rho, u);
+  equilibrium(L, rho, u, feq);
+  for (int k = 0; k < 9; ++k) sigma[k] = 0.0;
+  for (int a = 0; a < L.D; ++a)
+    for (int b = 0; b < L.D; ++b) {
+      double pi1 = 0.0;
+      for (int i = 0; i < L.Q; ++i) pi1 += (f[i] - feq[i]) * L.c[i][a] * L.c[i][b];
+      sigma[3 * a + b] = -(1.0 - beta) * pi1 - (a == b ? rho / 3.0 : 0.0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Storage rounding emulation: round-to-nearest-even of a double to a binary
+// format with p significant bits and minimum normal exponent emin (subnormals
+// kept), overflow to infinity.  Pinned against numpy float16 / bit-level bf16.
+// ---------------------------------------------------------------------------
+double round_format(double x, int p, int emin, double maxval) {
+  if (x == 0.0 || !std::isfinite(x)) return x;
+  int e = std::ilogb(x);
+  if (e < emin) e = emin;
+  const double quantum = std::ldexp(1.0, e - p + 1);
+  const double r = std::nearbyint(x / quantum) * quantum;
+  if (std::fabs(r) > maxval) return std::copysign(INFINITY, x);
+  return r;
+}
+
+double round_storage(int mode, double x) {
+  switch (mode) {
+    case 1: return (double)(float)x;                                   // binary32
+    case 2: return round_format(x, 11, -14, 65504.0);                  // binary16
+    case 3: return round_format(x, 8, -126, 3.3895313892515355e38);    // bfloat16
+    default: return x;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Prescribed-motion bodies (the structure solver is a stub with a motion law).
+//   kind 1 sphere (circle in 2D): params X0[3], R, A[3], omega, phase;
+//          centre X0 + A sin(omega t + phase), rigid translation.
+//   kind 2 flap (2D): params x_f, length l, thickness h, amplitude d0, omega,
+//          phase, y_base; solid where 0 <= s <= l and |x - x_c(s,t)| <= h/2 with
+//          s = y - y_base, x_c(s,t) = x_f + d0 sin(omega t + phase) (s/l)^2;
+//          velocity (d0 omega cos(omega t + phase)(s/l)^2, 0).
+//   kind 3 plates: params y_lo, y_hi, u_lo[3], u_hi[3]; solid where y < y_lo
+//          or y > y_hi; each plate moves tangentially with its own velocity.
+// Points on the surface count as solid.
+// ---------------------------------------------------------------------------
+struct Body {
+  int kind = 0;
+  double p[16] = {};
+};
+
+bool body_inside(const Body& b, int D, const double* x, double t) {
+  switch (b.kind) {
+    case 1: {
+      double r2 = 0.0;
+      for (int a = 0; a < D; ++a) {
+        const double c = b.p[a] + b.p[4 + a] * std::sin(b.p[7] * t + b.p[8]);
+        r2 += (x[a] - c) * (x[a] - c);
+      }
+      return r2 <= b.p[3] * b.p[3];
+    }
+    case 2: {
+      const double s = x[1] - b.p[6];
+      if (s < 0.0 || s > b.p[1]) return false;
+      const double xc = b.p[0] + b.p[3] * std::sin(b.p[4] * t + b.p[5]) * (s / b.p[1]) * (s / b.p[1]);
+      return std::fabs(x[0] - xc) <= 0.5 * b.p[2];
+    }
+    case 3:
+      return x[1] < b.p[0] || x[1] > b.p[1];
+    default:
+      return false;
+  }
+}
+
+void body_velocity(const Body& b, int D, const double* x, double t, double* v) {
+  v[0] = v[1] = v[2] = 0.0;
+  switch (b.kind) {
+    case 1:
+      for (int a = 0; a < D; ++a) v[a] = b.p[4 + a] * b.p[7] * std::cos(b.p[7] * t + b.p[8]);
+      break;
+    case 2: {
+      double s = x[1] - b.p[6];
+      s = std::min(std::max(s, 0.0), b.p[1]);
+      v[0] = b.p[3] * b.p[4] * std::cos(b.p[4] * t + b.p[5]) * (s / b.p[1]) * (s / b.p[1]);
+      break;
+    }
+    case 3: {
+      const double* u = (x[1] < 0.5 * (b.p[0] + b.p[1])) ? &b.p[2] : &b.p[5];
+      for (int a = 0; a < D; ++a) v[a] = u[a];
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Domain
+// ---------------------------------------------------------------------------
+enum Face { PERIODIC = 0, INLET = 1, OUTLET = 2, WALL = 3 };
+
+struct Domain {
+  const Lattice* L = nullptr;
+  int nx = 0, ny = 0, nz = 0;
+  long N = 0;
+  double nu = 0.0, beta = 0.0;
+  int collision = 0, trace_in_s = 0;
+  int face[6] = {};
+  double u_in[3] = {};
+  int inlet_profile = 0, ramp_steps = 0;
+  int storage = 0;
+  long step = 0;
+  Body body;
+  std::vector<double> A;      // post-collision state at time step
+  std::vector<double> fpre;   // pre-collision state of the last step
+  std::vector<uint8_t> solid; // geometry at time step
+  double gamma_min = 0.0, gamma_max = 0.0, gamma_sum = 0.0;
+  long gamma_count = 0;
+  long invalid_nodes = 0;
+  int nthreads = 0;
+};
+
+inline long node_index(const Domain& d, int x, int y, int z) {
+  return (long)x + (long)d.nx * ((long)y + (long)d.ny * (long)z);
+}
+
+// Link status of a neighbour coordinate.
+enum LinkKind { LINK_NODE = 0, LINK_WALL = 1, LINK_INLET = 2, LINK_OUTSIDE = 3, LINK_OUTLET = 4 };
+
+// Resolves the lattice site x + off (off in {-1,0,1}^3) under the face rules.
+// For streaming sources (streaming == true): periodic faces wrap, walls give a
+// missing link, the inlet and outlet mark a node that is overwritten by the
+// inflow or outflow condition (walls take precedence).  For
+// neighbour lookups (streaming == false) anything outside a periodic wrap is
+// LINK_OUTSIDE.
+int resolve(const Domain& d, const int* x, const int* off, bool streaming, long* out) {
+  const int n[3] = {d.nx, d.ny, d.nz};
+  int s[3];
+  bool wall = false, inlet = false, outlet = false, outside = false;
+  for (int a = 0; a < 3; ++a) {
+    s[a] = x[a] + off[a];
+    if (s[a] >= 0 && s[a] < n[a]) continue;
+    const int f = d.face[2 * a + (s[a] < 0 ? 0 : 1)];
+    if (f == PERIODIC) {
+      s[a] = (s[a] + n[a]) % n[a];
+    } else if (!streaming) {
+      outside = true;
+    } else if (f == WALL) {
+      wall = true;
+    } else if (f == OUTLET) {
+      outlet = true;
+    } else if (f == INLET) {
+      inlet = true;
+    }
+  }
+  if (outside) return LINK_OUTSIDE;
+  if (wall) return LINK_WALL;
+  if (inlet) return LINK_INLET;
+  if (outlet) return LINK_OUTLET;
+  *out = node_index(d, s[0], s[1], s[2]);
+  return LINK_NODE;
+}
+
+double ramp(const Domain& d, double t) {
+  if (d.ramp_steps <= 0) return 1.0;
+  const double tt = std::min(t, (double)d.ramp_steps);
+  return 0.5 * (1.0 - std::cos(M_PI * tt / d.ramp_steps));
+}
+
+// Inflow velocity at an inlet node: uniform u_in, or (inlet_profile == 1) the
+// parabolic channel profile 1.5 Ubar y(H-y)/(H/2)^2 of Sec. III.A.1 with
+// y = j + 1/2 measured from a wall half a spacing below the first node (and
+// the same factor along z in 3D); times the smooth ramp r(t).
+void inflow(const Domain& d, int y, int z, double t, double* u) {
+  double prof = 1.0;
+  if (d.inlet_profile == 1) {
+    const double yp = y + 0.5, H = d.ny;
+    prof = 1.5 * yp * (H - yp) / (0.25 * H * H);
+    if (d.L->D == 3) {
+      const double zp = z + 0.5, Z = d.nz;
+      prof *= 1.5 * zp * (Z - zp) / (0.25 * Z * Z);
+    }
+  }
+  const double r = ramp(d, t);
+  for (int a = 0; a < 3; ++a) u[a] = d.u_in[a] * prof * r;
+}
+
+void coords(const Domain& d, long n, int* x) {
+  x[0] = (int)(n % d.nx);
+  x[1] = (int)((n / d.nx) % d.ny);
+  x[2] = (int)(n / ((long)d.nx * d.ny));
+}
+
+bool inside_at(const Domain& d, const int* x, double t) {
+  const double p[3] = {(double)x[0], (double)x[1], (double)x[2]};
+  return body_inside(d.body, d.L->D, p, t);
+}
+
+// Wall fraction q in (0,1] along the link from fluid node x towards x - c
+// (which is inside the body): bisection on lambda for the first surface point
+// x - lambda c, 60 iterations.  Also returns the body velocity there.
+void cut_link(const Domain& d, const int* x, const int* c, double t, double* q, double* uw) {
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    const double p[3] = {x[0] - mid * c[0], x[1] - mid * c[1], x[2] - mid * c[2]};
+    if (body_inside(d.body, d.L->D, p, t)) hi = mid; else lo = mid;
+  }
+  *q = hi;
+  const double pw[3] = {x[0] - hi * c[0], x[1] - hi * c[1], x[2] - hi * c[2]};
+  body_velocity(d.body, d.L->D, pw, t, uw);
+}
+
+void apply_storage_rounding(Domain& d, long n) {
+  if (d.storage == 0) return;
+  const Lattice& L = *d.L;
+  double* f = &d.A[n * L.Q];
+  for (int i = 0; i < L.Q; ++i) f[i] = L.w[i] + round_storage(d.storage, f[i] - L.w[i]);
+}
+
+// One time step n -> n+1 (pull form of Eq. (1)):
+//   1 geometry at t_{n+1};  2 fresh-node refill;  3 streaming;
+//   4 Grad fill of missing populations;  5 inflow/outflow override;  6 collision;
+//   7 optional storage rounding.
+void step_once(Domain& d) {
+  const Lattice& L = *d.L;
+  const int Q = L.Q, D = L.D;
+  const long N = d.N;
+  const double t1 = (double)(d.step + 1);
+
+  // 1. Geometry at t_{n+1}.
+  std::vector<uint8_t> solid_new(N, 0);
+  if (d.body.kind != 0) {
+#pragma omp parallel for schedule(static) num_threads(d.nthreads)
+    for (long n = 0; n < N; ++n) {
+      int x[3];
+      coords(d, n, x);
+      solid_new[n] = inside_at(d, x, t1) ? 1 : 0;
+    }
+  }
+
+  // Lagged moments rho^n, u^n of the stored post-collision state.
+  std::vector<double> rho_n(N), u_n(3 * N);
+#pragma omp parallel for schedule(static) num_threads(d.nthreads)
+  for (long n = 0; n < N; ++n) moments(L, &d.A[n * Q], &rho_n[n], &u_n[3 * n]);
+
+  // 2. Fresh nodes (solid at n, fluid at n+1): A := f^eq(rho_bar, u_body), with
+  //    rho_bar the mean lagged density of neighbours that were fluid at n.
+  //    (The paper is silent on this; parity unpinned.)
+  if (d.body.kind != 0) {
+    for (long n = 0; n < N; ++n) {
+      if (!(d.solid[n] && !solid_new[n])) continue;
+      int x[3];
+      coords(d, n, x);
+      double sum = 0.0;
+      int cnt = 0;
+      for (int i = 0; i < Q; ++i) {
+        if (i == L.rest) continue;
+        long m;
+        if (resolve(d, x, L.c[i], false, &m) != LINK_NODE) continue;
+        if (d.solid[m]) continue;
+        sum += rho_n[m];
+        ++cnt;
+      }
+      const double rb = cnt ? sum / cnt : 1.0;
+      double ub[3];
+      const double p[3] = {(double)x[0], (double)x[1], (double)x[2]};
+      body_velocity(d.body, D, p, t1, ub);
+      equilibrium(L, rb, ub, &d.A[n * Q]);
+      rho_n[n] = rb;
+      for (int a = 0; a < 3; ++a) u_n[3 * n + a] = ub[a];
+    }
+  }
+
+  // 3.-5. Streaming, Grad fill and inflow, per fluid node.
+  std::vector<double>& F = d.fpre;
+  F.assign((size_t)N * Q, 0.0);
+#pragma omp parallel for schedule(static) num_threads(d.nthreads)
+  for (long n = 0; n < N; ++n) {
+    if (solid_new[n]) continue;
+    int x[3];
+    coords(d, n, x);
+    double* f = &F[n * Q];
+    bool missing[27] = {};
+    double q[27] = {}, uw[27][3] = {};
+    bool any_missing = false, inlet_node = false, outlet_node = false;
+    // 3. Pull streaming: f_i(x) = A_i(x - c_i).
+    for (int i = 0; i < Q; ++i) {
+      const int off[3] = {-L.c[i][0], -L.c[i][1], -L.c[i][2]};
+      long src;
+      const int k = resolve(d, x, off, true, &src);
+      if (k == LINK_INLET) { inlet_node = true; f[i] = 0.0; continue; }
+      if (k == LINK_OUTLET) { outlet_node = true; f[i] = 0.0; continue; }
+      if (k == LINK_WALL) {
+        missing[i] = true; any_missing = true; q[i] = 0.5;
+        continue;
+      }
+      if (solid_new[src]) {
+        missing[i] = true; any_missing = true;
+        cut_link(d, x, L.c[i], t1, &q[i], uw[i]);
+        continue;
+      }
+      f[i] = d.A[src * Q + i];
+    }
+    // 4. Grad's approximation for the missing populations (Sec. II.C.1).
+    //    Target density: bounce-back-implied density plus the wall-motion
+    //    term.  Target velocity: per missing link, the velocity at x
+    //    interpolated along c_i from the wall point x - q c_i and the lagged
+    //    velocities at x + c_i, x + 2 c_i (quadratic; linear if only x + c_i
+    //    is fluid; the wall velocity if neither is), averaged over the missing
+    //    links.  Velocity gradient: finite differences of the lagged velocity,
+    //    using the wall point on the cut side.  (Target-value formulas are a
+    //    reading of the paper's description; parity unpinned.)
+    if (any_missing && !inlet_node && !outlet_node) {
+      const double* Ax = &d.A[n * Q];
+      double rho_t = 0.0;
+      for (int i = 0; i < Q; ++i) {
+        if (!missing[i]) { rho_t += f[i]; continue; }
+        double cu = 0.0;
+        for (int a = 0; a < D; ++a) cu += L.c[i][a] * uw[i][a];
+        rho_t += Ax[Q - 1 - i] + 6.0 * L.w[i] * rho_n[n] * cu;
+      }
+      auto fluid_at = [&](const int* off, long* m) {
+        return resolve(d, x, off, false, m) == LINK_NODE && !solid_new[*m];
+      };
+      double ut[3] = {0.0, 0.0, 0.0};
+      int nm = 0;
+      for (int i = 0; i < Q; ++i) {
+        if (!missing[i]) continue;
+        const int o1[3] = {L.c[i][0], L.c[i][1], L.c[i][2]};
+        const int o2[3] = {2 * L.c[i][0], 2 * L.c[i][1], 2 * L.c[i][2]};
+        long m1, m2;
+        const double qq = q[i];
+        double ui[3];
+        if (fluid_at(o1, &m1) && fluid_at(o2, &m2)) {
+          // Lagrange weights at s = 0 for the nodes s = -q, 1, 2.
+          const double a0 = 2.0 / ((1.0 + qq) * (2.0 + qq));
+          const double a1 = 2.0 * qq / (1.0 + qq);
+          const double a2 = -qq / (2.0 + qq);
+          for (int a = 0; a < 3; ++a)
+            ui[a] = a0 * uw[i][a] + a1 * u_n[3 * m1 + a] + a2 * u_n[3 * m2 + a];
+        } else if (fluid_at(o1, &m1)) {
+          for (int a = 0; a < 3; ++a) ui[a] = (uw[i][a] + qq * u_n[3 * m1 + a]) / (1.0 + qq);
+        } else {
+          for (int a = 0; a < 3; ++a) ui[a] = uw[i][a];
+        }
+        for (int a = 0; a < 3; ++a) ut[a] += ui[a];
+        ++nm;
+      }
+      for (int a = 0; a < 3; ++a) ut[a] /= nm;
+      double grad[3][3] = {};   // grad[a][b] = d u_a / d x_b
+      for (int b = 0; b < D; ++b) {
+        // Population index of c = +e_b (its link to x - e_b) and c = -e_b.
+        const int ip = L.rest + (b == 0 ? 1 : b == 1 ? 3 : 9);
+        const int im = L.rest - (b == 0 ? 1 : b == 1 ? 3 : 9);
+        const bool cut_m = missing[ip];   // x - e_b is wall or body
+        const bool cut_p = missing[im];   // x + e_b is wall or body
+        int op1[3] = {0, 0, 0}, op2[3] = {0, 0, 0}, om1[3] = {0, 0, 0}, om2[3] = {0, 0, 0};
+        op1[b] = 1; op2[b] = 2; om1[b] = -1; om2[b] = -2;
+        long p1, p2, m1, m2;
+        const bool fp1 = fluid_at(op1, &p1), fp2 = fp1 && fluid_at(op2, &p2);
+        const bool fm1 = fluid_at(om1, &m1), fm2 = fm1 && fluid_at(om2, &m2);
+        for (int a = 0; a < D; ++a) {
+          double g = 0.0;
+          if (cut_m && cut_p) {
+            g = (uw[im][a] - uw[ip][a]) / (q[im] + q[ip]);
+          } else if (cut_m) {
+            const double qq = q[ip], w0 = uw[ip][a];
+            if (fp2)
+              g = -3.0 * w0 / ((1.0 + qq) * (2.0 + qq)) + u_n[3 * p1 + a] * (2.0 - qq) / (1.0 + qq) +
+                  u_n[3 * p2 + a] * (qq - 1.0) / (2.0 + qq);
+            else if (fp1)
+              g = (u_n[3 * p1 + a] - w0) / (1.0 + qq);
+          } else if (cut_p) {
+            const double qq = q[im], w0 = uw[im][a];
+            if (fm2)
+              g = 3.0 * w0 / ((1.0 + qq) * (2.0 + qq)) - u_n[3 * m1 + a] * (2.0 - qq) / (1.0 + qq) -
+                  u_n[3 * m2 + a] * (qq - 1.0) / (2.0 + qq);
+            else if (fm1)
+              g = (w0 - u_n[3 * m1 + a]) / (1.0 + qq);
+          } else if (fp1 && fm1) {
+            g = 0.5 * (u_n[3 * p1 + a] - u_n[3 * m1 + a]);
+          } else if (fp1) {
+            g = u_n[3 * p1 + a] - u_n[3 * n + a];
+          } else if (fm1) {
+            g = u_n[3 * n + a] - u_n[3 * m1 + a];
+          }
+          grad[a][b] = g;
+        }
+      }
+      double Pi[9] = {};
+      for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b)
+          Pi[3 * a + b] = (a == b ? rho_t / 3.0 : 0.0) + rho_t * ut[a] * ut[b] -
+                          rho_t / (6.0 * d.beta) * (grad[a][b] + grad[b][a]);
+      double fs[27];
+      grad_fstar(L, rho_t, ut, Pi, fs);
+      for (int i = 0; i < Q; ++i)
+        if (missing[i]) f[i] = fs[i];
+    }
+    // 5. Inflow node: all populations at equilibrium with the inflow velocity
+    //    and the lagged density of the interior neighbour x + e_x (so the
+    //    pressure level is set by the interior, not imposed at the inlet).
+    if (inlet_node) {
+      double ui[3];
+      inflow(d, x[1], x[2], t1, ui);
+      const int ex[3] = {1, 0, 0};
+      long m;
+      double rin = 1.0;
+      if (resolve(d, x, ex, false, &m) == LINK_NODE && !solid_new[m]) rin = rho_n[m];
+      equilibrium(L, rin, ui, f);
+    } else if (outlet_node) {
+      // Outflow node: equilibrium at the reference density 1 with the lagged
+      // velocity of the upstream neighbour x - e_x (pressure outlet).
+      const int mx[3] = {-1, 0, 0};
+      long m;
+      double uo[3] = {0.0, 0.0, 0.0};
+      if (resolve(d, x, mx, false, &m) == LINK_NODE && !solid_new[m])
+        for (int a = 0; a < 3; ++a) uo[a] = u_n[3 * m + a];
+      equilibrium(L, 1.0, uo, f);
+    }
+  }
+
+  // 6. Collision at every fluid node.
+  double gmin = 1e300, gmax = -1e300, gsum = 0.0;
+  long gcnt = 0, bad = 0;
+#pragma omp parallel for schedule(static) num_threads(d.nthreads) \
+    reduction(min : gmin) reduction(max : gmax) reduction(+ : gsum, gcnt, bad)
+  for (long n = 0; n < N; ++n) {
+    if (solid_new[n]) continue;
+    double g;
+    bad += collide(L, d.beta, d.collision, d.trace_in_s, &F[n * Q], &d.A[n * Q], &g);
+    gmin = std::min(gmin, g);
+    gmax = std::max(gmax, g);
+    gsum += g;
+    ++gcnt;
+    apply_storage_rounding(d, n);
+  }
+  d.gamma_min = gmin; d.gamma_max = gmax; d.gamma_sum = gsum; d.gamma_count = gcnt;
+  d.invalid_nodes += bad;
+  d.solid.swap(solid_new);
+  d.step += 1;
+}
+
+// Stress at a fluid node from the pre-collision state of the last step.
+void node_stress(const Domain& d, long n, double* sigma) {
+  stress(*d.L, d.beta, &d.fpre[n * d.L->Q], sigma);
+}
+
+// Stress at an off-lattice point p: (bi/tri)linear over the surrounding nodes
+// that are fluid, weights renormalised; if none has positive weight, the
+// nearest fluid node (Euclidean, first in z,y,x order on ties) in the 5^D box
+// around floor(p).  Returns false if no fluid node was found.
+bool point_stress(const Domain& d, const double* p, double* sigma) {
+  const int D = d.L->D;
+  int base[3] = {0, 0, 0};
+  double fr[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < D; ++a) {
+    base[a] = (int)std::floor(p[a]);
+    fr[a] = p[a] - base[a];
+  }
+  double acc[9] = {}, wsum = 0.0;
+  const int ncorner = 1 << D;
+  for (int k = 0; k < ncorner; ++k) {
+    int off[3] = {0, 0, 0};
+    double wgt = 1.0;
+    for (int a = 0; a < D; ++a) {
+      off[a] = (k >> a) & 1;
+      wgt *= off[a] ? fr[a] : 1.0 - fr[a];
+    }
+    if (wgt <= 0.0) continue;
+    long m;
+    if (resolve(d, base, off, false, &m) != LINK_NODE || d.solid[m]) continue;
+    double s[9];
+    node_stress(d, m, s);
+    for (int e = 0; e < 9; ++e) acc[e] += wgt * s[e];
+    wsum += wgt;
+  }
+  if (wsum > 0.0) {
+    for (int e = 0; e < 9; ++e) sigma[e] = acc[e] / wsum;
+    return true;
+  }
+  double best = 1e300;
+  long bestm = -1;
+  const int zr = (D == 3) ? 2 : 0;
+  for (int dz = -zr; dz <= zr; ++dz)
+    for (int dy = -2; dy <= 2; ++dy)
+      for (int dx = -2; dx <= 2; ++dx) {
+        const int off[3] = {dx, dy, dz};
+        long m;
+        if (resolve(d, base, off, false, &m) != LINK_NODE || d.solid[m]) continue;
+        const double q[3] = {(double)(base[0] + dx), (double)(base[1] + dy), (double)(base[2] + dz)};
+        double r2 = 0.0;
+        for (int a = 0; a < D; ++a) r2 += (q[a] - p[a]) * (q[a] - p[a]);
+        if (r2 < best) { best = r2; bestm = m; }
+      }
+  if (bestm < 0) {
+    for (int e = 0; e < 9; ++e) sigma[e] = 0.0;
+    return false;
+  }
+  node_stress(d, bestm, sigma);
+  return true;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C interface (ctypes).  All arrays are host double arrays owned by the caller.
+// Canonical population order for get/set: f[i * N + node], node x-fastest,
+// unshifted (full f_i).
+// ===========================================================================
+extern "C" {
+
+int orc_lattice(int Q, int* c, double* w) {
+  if (Q != 9 && Q != 27) return -1;
+  const Lattice& L = lattice(Q);
+  for (int i = 0; i < Q; ++i) {
+    for (int a = 0; a < 3; ++a) c[3 * i + a] = L.c[i][a];
+    w[i] = L.w[i];
+  }
+  return 0;
+}
+
+int orc_equilibrium(int Q, double rho, const double* u, double* feq) {
+  if (Q != 9 && Q != 27) return -1;
+  double uu[3] = {u[0], u[1], Q == 27 ? u[2] : 0.0};
+  equilibrium(lattice(Q), rho, uu, feq);
+  return 0;
+}
+
+int orc_moment_inverse(int Q, double* minv) {
+  if (Q != 9 && Q != 27) return -1;
+  const Lattice& L = lattice(Q);
+  for (int i = 0; i < Q; ++i)
+    for (int k = 0; k < Q; ++k) minv[i * Q + k] = L.Minv[i][k];
+  return 0;
+}
+
+int orc_split(int Q, const double* f, int trace_in_s, double* feq, double* ds, double* dh) {
+  if (Q != 9 && Q != 27) return -1;
+  const Lattice& L = lattice(Q);
+  double rho, u[3], delta[27];
+  moments(L, f, &rho, u);
+  equilibrium(L, rho, u, feq);
+  for (int i = 0; i < Q; ++i) delta[i] = f[i] - feq[i];
+  split(L, delta, trace_in_s, ds, dh);
+  return 0;
+}
+
+int orc_collide(int Q, double beta, int collision, int trace_in_s, const double* f, double* fout,
+                double* gamma) {
+  if (Q != 9 && Q != 27) return -1;
+  return collide(lattice(Q), beta, collision, trace_in_s, f, fout, gamma);
+}
+
+int orc_grad_fstar(int Q, double rho, const double* v, const double* Pi, double* out) {
+  if (Q != 9 && Q != 27) return -1;
+  grad_fstar(lattice(Q), rho, v, Pi, out);
+  return 0;
+}
+
+int orc_stress(int Q, double beta, const double* f, double* sigma) {
+  if (Q != 9 && Q != 27) return -1;
+  stress(lattice(Q), beta, f, sigma);
+  return 0;
+}
+
+int orc_round_storage(int mode, long n, const double* in, double* out) {
+  for (long k = 0; k < n; ++k) out[k] = round_storage(mode, in[k]);
+  return 0;
+}
+
+int orc_body_inside(int kind, const double* params, int D, const double* x, double t) {
+  Body b;
+  b.kind = kind;
+  for (int k = 0; k < 16; ++k) b.p[k] = params[k];
+  return body_inside(b, D, x, t) ? 1 : 0;
+}
+
+void* orc_create(int Q, int nx, int ny, int nz, double nu, int collision, int trace_in_s,
+                 const int* face, const double* u_in, int inlet_profile, int ramp_steps,
+                 int storage) {
+  if (Q != 9 && Q != 27) return nullptr;
+  if (nx < 1 || ny < 1 || nz < 1 || (Q == 9 && nz != 1) || !(nu > 0.0)) return nullptr;
+  Domain* d = new Domain;
+  d->L = &lattice(Q);
+  d->nx = nx; d->ny = ny; d->nz = nz;
+  d->N = (long)nx * ny * nz;
+  d->nu = nu;
+  d->beta = 1.0 / (6.0 * nu + 1.0);   // Eq. (7) with cs^2 = 1/3
+  d->collision = collision;
+  d->trace_in_s = trace_in_s;
+  for (int k = 0; k < 6; ++k) d->face[k] = face ? face[k] : PERIODIC;
+  for (int a = 0; a < 3; ++a) d->u_in[a] = u_in ? u_in[a] : 0.0;
+  d->inlet_profile = inlet_profile;
+  d->ramp_steps = ramp_steps;
+  d->storage = storage;
+  d->A.assign((size_t)d->N * Q, 0.0);
+  d->fpre.assign((size_t)d->N * Q, 0.0);
+  d->solid.assign(d->N, 0);
+#ifdef _OPENMP
+  d->nthreads = omp_get_max_threads();
+#else
+  d->nthreads = 1;
+#endif
+  return d;
+}
+
+void orc_destroy(void* h) { delete static_cast<Domain*>(h); }
+
+int orc_set_threads(void* h, int n) {
+  Domain* d = static_cast<Domain*>(h);
+  d->nthreads = n > 0 ? n : 1;
+  return 0;
+}
+
+// f := f^eq(rho, u) at every node; u planar [a * N + node].
+int orc_init_fields(void* h, const double* rho, const double* u) {
+  Domain* d = static_cast<Domain*>(h);
+  const Lattice& L = *d->L;
+  for (long n = 0; n < d->N; ++n) {
+    double uu[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < L.D; ++a) uu[a] = u[a * d->N + n];
+    equilibrium(L, rho[n], uu, &d->A[n * L.Q]);
+    apply_storage_rounding(*d, n);
+  }
+  d->fpre = d->A;
+  return 0;
+}
+
+int orc_set_populations(void* h, const double* f) {
+  Domain* d = static_cast<Domain*>(h);
+  const int Q = d->L->Q;
+  for (long n = 0; n < d->N; ++n)
+    for (int i = 0; i < Q; ++i) d->A[n * Q + i] = f[(long)i * d->N + n];
+  d->fpre = d->A;
+  return 0;
+}
+
+int orc_get_populations(void* h, double* f) {
+  const Domain* d = static_cast<const Domain*>(h);
+  const int Q = d->L->Q;
+  for (long n = 0; n < d->N; ++n)
+    for (int i = 0; i < Q; ++i) f[(long)i * d->N + n] = d->A[n * Q + i];
+  return 0;
+}
+
+// Pre-collision state of the last step, canonical order.
+int orc_get_precollision(void* h, double* f) {
+  const Domain* d = static_cast<const Domain*>(h);
+  const int Q = d->L->Q;
+  for (long n = 0; n < d->N; ++n)
+    for (int i = 0; i < Q; ++i) f[(long)i * d->N + n] = d->fpre[n * Q + i];
+  return 0;
+}
+
+// Sets the body and the geometry at the current time.
+int orc_set_body(void* h, int kind, const double* params) {
+  Domain* d = static_cast<Domain*>(h);
+  if (kind < 0 || kind > 3) return -1;
+  if (kind == 2 && d->L->D != 2) return -1;
+  d->body.kind = kind;
+  for (int k = 0; k < 16; ++k) d->body.p[k] = params ? params[k] : 0.0;
+  const double t = (double)d->step;
+  for (long n = 0; n < d->N; ++n) {
+    int x[3];
+    coords(*d, n, x);
+    d->solid[n] = (kind != 0 && inside_at(*d, x, t)) ? 1 : 0;
+  }
+  return 0;
+}
+
+int orc_step(void* h, int nsteps) {
+  Domain* d = static_cast<Domain*>(h);
+  for (int k = 0; k < nsteps; ++k) step_once(*d);
+  return d->invalid_nodes ? 1 : 0;
+}
+
+long orc_time(void* h) { return static_cast<Domain*>(h)->step; }
+
+int orc_solid(void* h, uint8_t* out) {
+  const Domain* d = static_cast<const Domain*>(h);
+  std::memcpy(out, d->solid.data(), d->N);
+  return 0;
+}
+
+// Moments of the stored state; solid nodes report rho = 0, u = 0.
+// totals: mass, momentum[3], gamma_min, gamma_mean, gamma_max (last step).
+int orc_moments(void* h, double* rho, double* u, double* totals) {
+  const Domain* d = static_cast<const Domain*>(h);
+  const Lattice& L = *d->L;
+  double mass = 0.0, mom[3] = {0.0, 0.0, 0.0};
+  for (long n = 0; n < d->N; ++n) {
+    double r = 0.0, uu[3] = {0.0, 0.0, 0.0};
+    if (!d->solid[n]) moments(L, &d->A[n * L.Q], &r, uu);
+    if (rho) rho[n] = r;
+    if (u)
+      for (int a = 0; a < L.D; ++a) u[a * d->N + n] = uu[a];
+    mass += r;
+    for (int a = 0; a < 3; ++a) mom[a] += r * uu[a];
+  }
+  if (totals) {
+    totals[0] = mass;
+    for (int a = 0; a < 3; ++a) totals[1 + a] = mom[a];
+    totals[4] = d->gamma_count ? d->gamma_min : 2.0;
+    totals[5] = d->gamma_count ? d->gamma_sum / d->gamma_count : 2.0;
+    totals[6] = d->gamma_count ? d->gamma_max : 2.0;
+  }
+  return d->invalid_nodes ? 1 : 0;
+}
+
+// Wall force (Sec. II.C.2) from the pre-collision stress of the last step:
+// for each quadrature point (x_q, n_q, w_q) with n_q the outward body normal,
+// sigma is sampled at x_q + n_q and x_q + 2 n_q, linearly extrapolated to the
+// surface, sigma_q = 2 sigma(p1) - sigma(p2); traction t_q = sigma_q n_q; the
+// force of the fluid on the body is F = sum_q w_q t_q.  The extrapolation
+// scheme is a reading of "similar to Kollmannsberger et al."; parity unpinned.
+// Arrays are point-major with D components (xq[q*D + a]).
+int orc_wall_force(void* h, const double* xq, const double* nq, const double* wq, int nqp,
+                   double* traction, double* force) {
+  const Domain* d = static_cast<const Domain*>(h);
+  const int D = d->L->D;
+  double F[3] = {0.0, 0.0, 0.0};
+  int missing = 0;
+  for (int q = 0; q < nqp; ++q) {
+    double s1[9], s2[9], p1[3] = {0, 0, 0}, p2[3] = {0, 0, 0}, nv[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) {
+      nv[a] = nq[q * D + a];
+      p1[a] = xq[q * D + a] + nv[a];
+      p2[a] = xq[q * D + a] + 2.0 * nv[a];
+    }
+    if (!point_stress(*d, p1, s1)) ++missing;
+    if (!point_stress(*d, p2, s2)) ++missing;
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < D; ++a)
+      for (int b = 0; b < D; ++b) t[a] += (2.0 * s1[3 * a + b] - s2[3 * a + b]) * nv[b];
+    for (int a = 0; a < D; ++a) {
+      if (traction) traction[q * D + a] = t[a];
+      F[a] += wq[q] * t[a];
+    }
+  }
+  for (int a = 0; a < 3; ++a) force[a] = F[a];
+  return missing ? 2 : 0;
+}
+
+// Streaming only (no boundary fill, no collision), for the brute-force
+// permutation test: A := pulled A (periodic faces only).
+int orc_stream_only(void* h) {
+  Domain* d = static_cast<Domain*>(h);
+  const Lattice& L = *d->L;
+  std::vector<double> B(d->A.size());
+  for (long n = 0; n < d->N; ++n) {
+    int x[3];
+    coords(*d, n, x);
+    for (int i = 0; i < L.Q; ++i) {
+      const int off[3] = {-L.c[i][0], -L.c[i][1], -L.c[i][2]};
+      long src;
+      if (resolve(*d, x, off, true, &src) != LINK_NODE) return -1;
+      B[n * L.Q + i] = d->A[src * L.Q + i];
+    }
+  }
+  d->A.swap(B);
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,192 @@
+"""Domain-level pins of the CPU oracle: closed-form flows, invariants and brute
+force on tiny grids (Sec. II.A viscosity relation, Sec. II.C.1 Grad walls,
+Sec. II.C.2 wall stress)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+def test_streaming_is_the_lattice_shift(orc):
+    """Pull streaming f_i(x) = A_i(x - c_i) on a periodic 5x4x3 grid equals a
+    cyclic shift of each population array by c_i (brute force)."""
+    Q, nx, ny, nz = 27, 5, 4, 3
+    d = orc.Domain(Q, nx, ny, nz, 0.1)
+    c, _ = orc.lattice(Q)
+    A = np.random.default_rng(0).uniform(size=(Q, nz, ny, nx))
+    d.set_populations(A.reshape(Q, -1))
+    d.stream_only()
+    got = d.get_populations().reshape(Q, nz, ny, nx)
+    for i in range(Q):
+        exp = np.roll(A[i], shift=(c[i, 2], c[i, 1], c[i, 0]), axis=(0, 1, 2))
+        assert np.array_equal(got[i], exp)
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_uniform_equilibrium_is_fixed_point(orc, Q):
+    n = 6
+    D = 2 if Q == 9 else 3
+    N = n ** D
+    d = orc.Domain(Q, n, n, n if D == 3 else 1, 0.02)
+    u0 = np.array([0.05, -0.03, 0.02])[:D]
+    d.init_fields(np.full(N, 1.02), np.repeat(u0[:, None], N, axis=1))
+    f0 = d.get_populations()
+    d.step(10)
+    assert np.allclose(d.get_populations(), f0, rtol=0, atol=1e-15)
+
+
+def test_tg2d_decay_and_second_order(orc):
+    """2D Taylor-Green: velocity decays as exp(-2 nu k^2 t) with the viscosity of
+    Eq. 7; error against the analytic field <= 2.5e-3 at 64^2 / 500 steps and
+    second-order convergence over 32, 64, 128 at fixed nu t k^2."""
+    errs = []
+    for n in (32, 64, 128):
+        steps = 500 * n * n // (64 * 64)
+        rho, u = W.taylor_green_2d(n, 0.02)
+        d = orc.Domain(9, n, n, 1, 0.01)
+        d.init_fields(rho, u)
+        d.step(steps)
+        r, uu, tot = d.moments()
+        ref = u * W.taylor_green_2d_decay(0.01, n, steps)
+        errs.append(np.linalg.norm(uu - ref) / np.linalg.norm(ref))
+        # mass and momentum conserved to round-off
+        assert abs(tot["mass"] - rho.sum()) < 1e-12 * rho.sum()
+        assert np.all(np.abs(tot["momentum"]) < 1e-11)
+    assert errs[1] <= 2.5e-3
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert min(orders) >= 1.9, (errs, orders)
+
+
+def test_tg2d_kbc_close_to_lbgk_when_resolved(orc):
+    """On a resolved smooth flow KBC stays close to LBGK (gamma near 2)."""
+    n = 32
+    rho, u = W.taylor_green_2d(n, 0.02)
+    out = []
+    for coll in (0, 1):
+        d = orc.Domain(9, n, n, 1, 0.01, collision=coll)
+        d.init_fields(rho, u)
+        d.step(200)
+        out.append(d.moments()[1])
+    assert np.linalg.norm(out[0] - out[1]) / np.linalg.norm(out[1]) < 1e-3
+
+
+@pytest.mark.parametrize("qlo,qhi", [(0.25, 0.75), (0.5, 0.5), (0.75, 0.25)])
+def test_couette_through_grad_walls(orc, qlo, qhi):
+    """Moving-plate Couette flow with walls cutting links at fraction q: Grad's
+    boundary (Sec. II.C.1) reproduces the linear profile, and the stress-based
+    wall force (Sec. II.C.2) gives the shear rho nu U / h on each plate."""
+    ny, nx, U, nu = 14, 4, 0.02, 0.1
+    ylo, yhi = 1 - qlo, (ny - 2) + qhi
+    d = orc.Domain(9, nx, ny, 1, nu)
+    N = nx * ny
+    d.init_fields(np.ones(N), np.zeros((2, N)))
+    d.set_body(W.BODY_PLATES, W.plates_params(ylo, yhi, (0, 0, 0), (U, 0, 0)))
+    d.step(5000)
+    rho, u, tot = d.moments()
+    ux = u[0].reshape(ny, nx)[:, 0]
+    y = np.arange(ny)
+    exact = U * (y - ylo) / (yhi - ylo)
+    assert np.max(np.abs(ux[1:-1] - exact[1:-1])) < 1e-5 * U
+    assert np.max(np.abs(u[1])) < 1e-5 * U       # no flux through the plates
+    tau = nu * U / (yhi - ylo)
+    F, tr, st = d.wall_force(*W.plate_quadrature(ylo, +1.0, nx))
+    assert st == 0
+    assert abs(F[0] / nx - tau) < 1e-3 * tau
+    assert abs(F[1] / nx + 1 / 3) < 1e-4          # pressure pushes on the plate
+    F2, _, _ = d.wall_force(*W.plate_quadrature(yhi, -1.0, nx))
+    assert abs(F2[0] / nx + tau) < 1e-3 * tau
+
+
+def test_poiseuille_channel_inlet_outlet_walls(orc):
+    """Channel with parabolic velocity inflow, equilibrium pressure outflow and
+    no-slip walls half a spacing outside the first/last rows (Sec. III.A.1
+    inflow profile): the developed profile converges to the parabola at
+    better than first order (Grad boundary, Sec. II.C.1), and the mass flux is
+    the same through every cross-section."""
+    ubar, nu = 0.02, 0.05
+    errs = []
+    for H in (8, 16):
+        nx, ny = 4 * H, H
+        d = orc.Domain(9, nx, ny, 1, nu, faces=["inlet", "outlet", "wall", "wall", "periodic",
+                                                "periodic"], u_in=(ubar, 0, 0), inlet_profile=1)
+        N = nx * ny
+        d.init_fields(np.ones(N), np.zeros((2, N)))
+        d.step(int(6 * H * H / nu))
+        rho, u, tot = d.moments()
+        ux = u[0].reshape(ny, nx)
+        yp = np.arange(ny) + 0.5
+        para = 1.5 * ubar * yp * (ny - yp) / (0.25 * ny * ny)
+        x = nx // 2
+        errs.append(np.max(np.abs(ux[:, x] / ux[:, x].mean() - para / para.mean())))
+        assert abs(ux[:, x].mean() / ubar - 1) < 5e-3
+        flux = (rho.reshape(ny, nx) * ux).sum(axis=0)[2:-2]
+        assert (flux.max() - flux.min()) / flux.mean() < 5e-3
+        assert np.max(np.abs(u[1].reshape(ny, nx)[:, H:-H])) < 1e-3 * ubar
+    assert errs[1] < 4e-3
+    assert math.log2(errs[0] / errs[1]) > 1.5, errs
+
+
+def test_resting_sphere_is_fixed_point_and_force_free(orc):
+    """Body and fluid at rest: Grad's fill returns the rest populations, so the
+    state does not change, and the force reduces to -p sum w n = 0."""
+    n = 16
+    d = orc.Domain(27, n, n, n, 0.05)
+    N = n ** 3
+    d.init_fields(np.ones(N), np.zeros((3, N)))
+    center = (7.3, 8.1, 7.7)
+    d.set_body(W.BODY_SPHERE, W.sphere_params(center, 4.2))
+    solid = d.solid().astype(bool)
+    f0 = d.get_populations()
+    d.step(5)
+    f1 = d.get_populations()
+    assert np.allclose(f1[:, ~solid], f0[:, ~solid], rtol=0, atol=1e-15)
+    xq, nq, wq = W.sphere_quadrature(center, 4.2, subdiv=3)
+    F, tr, st = d.wall_force(xq, nq, wq)
+    assert st == 0
+    assert np.max(np.abs(F)) < 1e-12
+    assert np.allclose(tr, -nq / 3, atol=1e-14)
+
+
+def test_moving_sphere_drag_opposes_motion(orc):
+    """A sphere pushed through fluid at rest feels a force against its motion,
+    and the fluid near it is set in motion along it."""
+    n = 24
+    d = orc.Domain(27, n, n, n, 0.05)
+    N = n ** 3
+    d.init_fields(np.ones(N), np.zeros((3, N)))
+    center = (11.6, 12.2, 11.9)
+    amp, period = 3.0, 600.0
+    d.set_body(W.BODY_SPHERE, W.sphere_params(center, 4.0, (amp, 0, 0), period))
+    d.step(30)
+    t = d.time
+    cx = center[0] + amp * math.sin(2 * math.pi * t / period)
+    xq, nq, wq = W.sphere_quadrature((cx, center[1], center[2]), 4.0, subdiv=3)
+    F, tr, st = d.wall_force(xq, nq, wq)
+    assert F[0] < 0
+    assert abs(F[1]) < 0.2 * abs(F[0]) and abs(F[2]) < 0.2 * abs(F[0])
+    rho, u, tot = d.moments()
+    assert tot["momentum"][0] > 0
+    assert not tot["invalid"]
+
+
+def test_flap_channel_runs_and_stays_valid(orc):
+    """One small flap channel (the batched workload's building block) stays a
+    valid state (rho > 0, |u| < 1) over a few hundred steps."""
+    ch = W.flap_channels(count=1, seed=2375)[0]
+    d = orc.Domain(9, 128, 64, 1, ch["nu"], faces=ch["faces"], u_in=ch["u_in"],
+                   inlet_profile=1)
+    N = 128 * 64
+    d.init_fields(np.ones(N), np.zeros((2, N)))
+    kind, p = ch["body"]
+    p = p.copy()
+    p[0] = 32.0
+    p[1] = min(p[1], 20.0)
+    d.set_body(kind, p)
+    assert d.solid().sum() > 0
+    d.step(300)
+    rho, u, tot = d.moments()
+    assert not tot["invalid"]
+    fl = d.solid() == 0
+    assert rho[fl].min() > 0.9 and np.abs(u[:, fl]).max() < 0.2
