@@ -1,0 +1,221 @@
+/*
+ * lbm.h -- C ABI of the MI355X KBC lattice Boltzmann library.
+ *
+ * The library advances the entropic multi-relaxation-time (KBC) lattice
+ * Boltzmann equation of Dorschner, Chikatamarla & Karlin, "Fluid-structure
+ * interaction with the entropic lattice Boltzmann method" (Sec. II.A), with
+ * Grad's-approximation reconstruction of missing populations at moving walls
+ * (Sec. II.C.1) and the stress-based wall force on a body (Sec. II.C.2), on one
+ * AMD Instinct MI355X (gfx950).  The call order of one fluid-structure
+ * coupling step (Sec. II.C, conventional serial staggered scheme) is
+ *     lbm_step -> lbm_wall_force -> (structure solve on the host) -> lbm_set_geometry.
+ *
+ * Conventions (all functions):
+ *   - Return an lbm_status: LBM_OK (0) on success, a negative code on error.
+ *     lbm_last_error() gives a human-readable message for the last failure.
+ *   - Lattice units throughout.  Lattices: D2Q9 and D3Q27, the tensor products
+ *     of D1Q3 (weights 2/3, 1/6, 1/6 per axis; speed of sound 1/sqrt(3)).
+ *     Velocity index i = (cx+1) + 3(cy+1) + 9(cz+1); opposite index Q-1-i.
+ *   - Host arrays are owned by the caller; the library copies in before
+ *     returning and copies out before returning from synchronous calls.
+ *   - Node order is x-fastest: node = x + nx*(y + ny*z).  Vector fields are
+ *     planar: u[a*N + node].  Population arrays are population-major:
+ *     f[i*N + node], full (unshifted) f_i in double precision.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Device memory is owned by the context unless allocation callbacks are
+ *     given (then the callback owner must outlive the context).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int lbm_status;
+#define LBM_OK 0
+#define LBM_ERR_INVALID (-1)     /* bad argument or description */
+#define LBM_ERR_OOM (-2)         /* device allocation failed */
+#define LBM_ERR_DEVICE (-3)      /* a HIP runtime call failed */
+#define LBM_ERR_NONFINITE (-4)   /* a node reached a non-finite or invalid state */
+#define LBM_ERR_GEOMETRY (-5)    /* body does not fit the domain */
+#define LBM_ERR_UNSUPPORTED (-6) /* valid request this build does not provide */
+
+/* Lattice (value = number of velocities Q). */
+#define LBM_D2Q9 9
+#define LBM_D3Q27 27
+
+/* Population storage.  All forms store the deviation f_i - W_i from the rest
+ * state; F16/BF16 store it in 16 bits and compute in FP32, F32 stores and
+ * computes in FP32, F64 stores and computes in FP64. */
+#define LBM_F64 0
+#define LBM_F32 1
+#define LBM_F16_SHIFTED 2
+#define LBM_BF16_SHIFTED 3
+
+/* Collision: entropic KBC (stabiliser gamma per node, Sec. II.A Eq. 6) or
+ * LBGK (gamma fixed to 2, relaxation rate 2 beta). */
+#define LBM_KBC 0
+#define LBM_LBGK 1
+
+/* Face conditions, faces ordered -x, +x, -y, +y, -z, +z.  PERIODIC must be
+ * paired; INLET is allowed on -x only, OUTLET on +x only.
+ *   INLET : equilibrium at the inflow velocity and the lagged density of the
+ *           interior neighbour (parabolic profile option, smooth ramp).
+ *   OUTLET: equilibrium at density 1 and the lagged velocity of the upstream
+ *           neighbour.
+ *   WALL  : resting no-slip wall half a spacing outside the face, filled by
+ *           Grad's approximation like any cut link (q = 1/2). */
+#define LBM_FACE_PERIODIC 0
+#define LBM_FACE_INLET 1
+#define LBM_FACE_OUTLET 2
+#define LBM_FACE_WALL 3
+
+/* Prescribed-motion bodies (the structure solver is a host-side stub).
+ *   SPHERE (circle in 2D): params X0[3], R, A[3], omega, phase;
+ *           centre X0 + A sin(omega t + phase), rigid translation.
+ *   FLAP (2D): params x_f, length l, thickness h, amplitude d0, omega, phase,
+ *           y_base; solid where 0 <= s <= l and |x - x_c(s,t)| <= h/2, with
+ *           s = y - y_base and x_c = x_f + d0 sin(omega t + phase) (s/l)^2.
+ *   PLATES: params y_lo, y_hi, u_lo[3], u_hi[3]; solid where y < y_lo or
+ *           y > y_hi; each plate slides tangentially with its velocity.
+ * Points on the surface count as solid.  Time t is the step count. */
+#define LBM_BODY_NONE 0
+#define LBM_BODY_SPHERE 1
+#define LBM_BODY_FLAP 2
+#define LBM_BODY_PLATES 3
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef struct {
+  int lattice;        /* LBM_D2Q9 or LBM_D3Q27 */
+  int nx, ny, nz;     /* >= 1 each; nz == 1 for D2Q9 */
+  double nu;          /* kinematic viscosity > 0; beta = 1/(6 nu + 1) (Sec. II.A, Eq. 7) */
+  int storage;        /* LBM_F64 .. LBM_BF16_SHIFTED; same for every instance */
+  int collision;      /* LBM_KBC or LBM_LBGK */
+  int kbc_trace_in_s; /* 0: trace of the second moments relaxes with gamma (part of h);
+                         1: it relaxes with the shear part s */
+  int face[6];        /* LBM_FACE_* for -x,+x,-y,+y,-z,+z */
+  double u_in[3];     /* inflow velocity (mean velocity for the parabolic profile) */
+  int inlet_profile;  /* 0 uniform, 1 parabolic 1.5 U y(H-y)/(H/2)^2 (Sec. III.A.1) */
+  int ramp_steps;     /* inflow ramp 0.5 (1 - cos(pi min(t,T)/T)); 0 = none */
+} lbm_instance_desc;
+
+typedef struct {
+  int device;                              /* HIP device ordinal */
+  void* hip_stream;                        /* hipStream_t to launch on; NULL = own stream */
+  void* (*alloc)(size_t bytes, void* ctx); /* optional device allocator (e.g. PyTorch) */
+  void (*free)(void* ptr, void* ctx);      /* matching release; both or neither */
+  void* alloc_ctx;                         /* passed back to alloc/free */
+  int use_graph;                           /* 1: replay lbm_step through a captured hipGraph */
+} lbm_device_opts;
+
+typedef struct {
+  int kind;          /* LBM_BODY_* */
+  double params[16]; /* layout per kind, see above */
+} lbm_body;
+
+typedef struct {
+  double mass;        /* sum of rho over fluid nodes (FP64) */
+  double momentum[3]; /* sum of rho u over fluid nodes (FP64) */
+  double gamma_min, gamma_mean, gamma_max; /* over fluid nodes of the last stats step */
+  double fp64_gamma_fraction; /* share of nodes whose gamma used the FP64 path */
+  int64_t step;       /* steps taken */
+} lbm_totals;
+
+/* Creates a context holding n_instances lattices that are stepped together
+ * (one batched launch per kernel).  All instances must share lattice and
+ * storage.  Populations start at the rest state f_i = W_i.  opts may be NULL
+ * (device 0, own stream, internal allocation, graphs on).
+ * Errors: LBM_ERR_INVALID (bad description), LBM_ERR_OOM, LBM_ERR_DEVICE. */
+lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances,
+                      const lbm_device_opts* opts, lbm_ctx** out);
+
+/* Releases every device resource of the context.  NULL is accepted. */
+lbm_status lbm_destroy(lbm_ctx* ctx);
+
+/* Sets instance inst to the entropic equilibrium f^eq(rho, u) at every node
+ * (Sec. II.A, Eqs. 4-5).  rho: N doubles; u: D*N doubles, planar.
+ * Requires rho > 0 and |u_a| < 1 (else LBM_ERR_INVALID).  Synchronous. */
+lbm_status lbm_init_fields(lbm_ctx* ctx, int inst, const double* rho, const double* u);
+
+/* Replaces the body of instance inst; the geometry at the current time is
+ * built on the device and thereafter follows the motion law on the device,
+ * so lbm_step needs no host update.  body == NULL or kind NONE removes it.
+ * Errors: LBM_ERR_INVALID (unknown kind, flap in 3D), LBM_ERR_GEOMETRY (the
+ * body's swept region does not fit inside the domain with a 2-node margin
+ * along periodic axes). */
+lbm_status lbm_set_geometry(lbm_ctx* ctx, int inst, const lbm_body* body);
+
+/* Advances every instance by n_steps >= 0 steps (Sec. II.A, Eq. 1, pull form:
+ * geometry update, fresh-node refill, streaming, Grad fill, face conditions,
+ * KBC collision).  Asynchronous on the context stream.  Returns
+ * LBM_ERR_NONFINITE if a previous step set the device error word (checked
+ * without a device sync at most every 64 steps). */
+lbm_status lbm_step(lbm_ctx* ctx, int n_steps);
+
+/* Density and velocity of the stored (post-collision) state of instance inst;
+ * they equal the moments the last collision used, since it conserves them.
+ * Solid nodes report rho = 0, u = 0.  rho: N doubles, u: D*N doubles, tot:
+ * totals; any output may be NULL.  Synchronous.  Returns LBM_ERR_NONFINITE if
+ * the device error word is set (outputs are still written). */
+lbm_status lbm_moments(lbm_ctx* ctx, int inst, double* rho, double* u, lbm_totals* tot);
+
+/* Force of the fluid on the body of instance inst (Sec. II.C.2): for each
+ * quadrature point (xq, nq outward unit body normal, wq weight) the
+ * pre-collision stress sigma = -p I - (1-beta) Pi^(1) of the last step is
+ * sampled at xq + nq and xq + 2 nq (linear over fluid nodes), extrapolated
+ * to the surface as 2 sigma(p1) - sigma(p2), and t_q = sigma_q nq.
+ * force = sum_q wq t_q (FP64, deterministic order).  Arrays are point-major
+ * with D components (xq[q*D + a]).  traction (n_q*D doubles) may be NULL.
+ * Requires at least one step since the last geometry or population change
+ * (else LBM_ERR_INVALID).  Synchronous. */
+lbm_status lbm_wall_force(lbm_ctx* ctx, int inst, const double* xq, const double* nq,
+                          const double* wq, int n_q, double* traction, double force[3]);
+
+/* Checkpoint: copies the populations of instance inst to / from the host
+ * (Q*N doubles, population-major, full f_i).  A set is rounded to the
+ * storage format.  Resuming from get -> set is bitwise exact. */
+lbm_status lbm_get_populations(lbm_ctx* ctx, int inst, double* f);
+lbm_status lbm_set_populations(lbm_ctx* ctx, int inst, const double* f);
+
+/* Switches per-step statistics (gamma min/mean/max, FP64-path share) on or
+ * off; off by default because it adds a reduction to every step. */
+lbm_status lbm_set_stats(lbm_ctx* ctx, int enabled);
+
+/* Launch mode: 0 = one batched launch per kernel for all instances (default),
+ * 1 = one launch per instance (reference for the batched form). */
+lbm_status lbm_set_launch_mode(lbm_ctx* ctx, int mode);
+
+/* Times the candidate tile shapes of the bulk kernel on this context's
+ * instances (a few steps each, state restored afterwards) and keeps the
+ * fastest.  cache_path (nullable) names a JSON file of earlier results keyed
+ * by lattice, storage, sizes and device; it is read first and updated.
+ * chosen (nullable) receives the index of the chosen variant. */
+lbm_status lbm_autotune(lbm_ctx* ctx, const char* cache_path, int* chosen);
+
+/* Selects a bulk-kernel variant by index (0 .. lbm_variant_count()-1). */
+lbm_status lbm_set_variant(lbm_ctx* ctx, int variant);
+int lbm_variant_count(void);
+const char* lbm_variant_name(int variant);
+
+/* Information: nodes of instance inst (N), total nodes, algorithmic bytes per
+ * lattice update (2 Q sizeof(storage)), steps taken. */
+lbm_status lbm_info(const lbm_ctx* ctx, int inst, int64_t* nodes, int64_t* total_nodes,
+                    int* bytes_per_update, int64_t* step);
+
+/* Waits for all work on the context stream.  Returns LBM_ERR_NONFINITE if the
+ * device error word is set. */
+lbm_status lbm_synchronize(lbm_ctx* ctx);
+
+const char* lbm_status_string(lbm_status s);
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,1007 @@
+// Host engine behind the C ABI of include/lbm.h: instance tables, device
+// memory layout, work lists, the per-step launch schedule (optionally replayed
+// from a captured hipGraph), synchronous queries and the tile autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "kernels.hpp"
+
+using namespace kbc;
+
+struct lbm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  void* (*ualloc)(size_t, void*) = nullptr;
+  void (*ufree)(void*, void*) = nullptr;
+  void* actx = nullptr;
+  int use_graph = 1;
+
+  int Q = 27, D = 3, storage = LBM_F32, esize = 4;
+  const Ops* ops = nullptr;
+  int n_inst = 0;
+  std::vector<lbm_instance_desc> desc;
+  std::vector<InstDev> hinst;
+  std::vector<int> moving;        // body moves (geometry changes every step)
+  std::vector<char> has_body;
+  std::vector<char> force_valid;
+  int64_t total_nodes = 0;
+  size_t pop_elems = 0;           // elements per population buffer
+
+  void* buf[2] = {nullptr, nullptr};
+  int cur = 0;                    // buf[cur] holds the current state
+  uint8_t* flags = nullptr;
+  size_t flag_bytes = 0;
+  InstDev* dinst = nullptr;
+  int64_t* dclock = nullptr;
+  uint32_t* derr = nullptr;
+  uint32_t* herr = nullptr;       // pinned mirror of the error word
+  hipEvent_t err_event = nullptr;
+  bool err_pending = false;
+  int64_t step = 0;
+
+  int variant = 0;
+  std::vector<Tile> tiles;
+  std::vector<int> tile_first, tile_count;
+  Tile* dtiles = nullptr;
+  std::vector<Region> regions;
+  std::vector<BoxTile> btiles, gtiles;
+  std::vector<int> bt_first, bt_count;
+  Region* dregions = nullptr;
+  BoxTile* dbtiles = nullptr;
+  BoxTile* dgtiles = nullptr;
+  bool time_dependent = false;
+
+  int stats_enabled = 0;
+  StatPartial* dstats = nullptr;
+  size_t dstats_cap = 0;
+  int launch_mode = 0;
+
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  bool graph_failed = false;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf; else g_create_error = buf;
+  return s;
+}
+
+#define HIPCHECK(ctx, expr)                                                                    \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail((ctx), LBM_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+lbm_status dev_alloc(lbm_ctx* c, size_t bytes, void** p) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  if (c->ualloc) {
+    *p = c->ualloc(bytes, c->actx);
+    if (!*p) return fail(c, LBM_ERR_OOM, "allocator callback returned NULL for %zu bytes", bytes);
+    return LBM_OK;
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(c, LBM_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  return LBM_OK;
+}
+
+void dev_free(lbm_ctx* c, void* p) {
+  if (!p) return;
+  if (c->ufree) c->ufree(p, c->actx);
+  else (void)hipFree(p);
+}
+
+template <typename T>
+lbm_status upload(lbm_ctx* c, T** dptr, const std::vector<T>& h) {
+  dev_free(c, *dptr);
+  *dptr = nullptr;
+  lbm_status st = dev_alloc(c, std::max<size_t>(h.size(), 1) * sizeof(T), (void**)dptr);
+  if (st) return st;
+  if (!h.empty())
+    HIPCHECK(c, hipMemcpyAsync(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice,
+                               c->stream));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int storage_bytes(int st) {
+  switch (st) {
+    case LBM_F64: return 8;
+    case LBM_F32: return 4;
+    default: return 2;
+  }
+}
+
+bool valid_faces(const lbm_instance_desc& d) {
+  for (int k = 0; k < 6; ++k)
+    if (d.face[k] < LBM_FACE_PERIODIC || d.face[k] > LBM_FACE_WALL) return false;
+  for (int a = 0; a < 3; ++a) {
+    const bool p0 = d.face[2 * a] == LBM_FACE_PERIODIC, p1 = d.face[2 * a + 1] == LBM_FACE_PERIODIC;
+    if (p0 != p1) return false;
+  }
+  for (int k = 0; k < 6; ++k) {
+    if (d.face[k] == LBM_FACE_INLET && k != 0) return false;
+    if (d.face[k] == LBM_FACE_OUTLET && k != 1) return false;
+  }
+  if (d.lattice == LBM_D2Q9 && (d.face[4] != LBM_FACE_PERIODIC || d.face[5] != LBM_FACE_PERIODIC))
+    return false;
+  return true;
+}
+
+bool needs_flags(const lbm_instance_desc& d) {
+  for (int k = 0; k < 6; ++k)
+    if (d.face[k] != LBM_FACE_PERIODIC) return true;
+  return false;
+}
+
+// Swept box of a body over its whole motion, with a 2-node margin; false if
+// it leaves the domain along a periodic axis.
+bool body_box(const lbm_ctx* c, int k, const lbm_body& b, int lo[3], int hi[3]) {
+  const lbm_instance_desc& d = c->desc[k];
+  const int n[3] = {d.nx, d.ny, d.nz};
+  double blo[3] = {0, 0, 0}, bhi[3] = {(double)d.nx, (double)d.ny, (double)d.nz};
+  const double* p = b.params;
+  if (b.kind == LBM_BODY_SPHERE) {
+    for (int a = 0; a < c->D; ++a) {
+      blo[a] = p[a] - std::fabs(p[4 + a]) - p[3];
+      bhi[a] = p[a] + std::fabs(p[4 + a]) + p[3];
+    }
+  } else if (b.kind == LBM_BODY_FLAP) {
+    blo[0] = p[0] - 0.5 * p[2] - std::fabs(p[3]);
+    bhi[0] = p[0] + 0.5 * p[2] + std::fabs(p[3]);
+    blo[1] = p[6];
+    bhi[1] = p[6] + p[1];
+  } else if (b.kind == LBM_BODY_PLATES) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = 0;
+      hi[a] = n[a];
+    }
+    return true;
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (a >= c->D) {
+      lo[a] = 0;
+      hi[a] = 1;
+      continue;
+    }
+    int l = (int)std::floor(blo[a]) - 2, h = (int)std::ceil(bhi[a]) + 3;
+    const bool periodic = d.face[2 * a] == LBM_FACE_PERIODIC;
+    if (l < 0 || h > n[a]) {
+      if (periodic) return false;
+      l = std::max(l, 0);
+      h = std::min(h, n[a]);
+    }
+    if (h <= l) {
+      l = 0;
+      h = 0;
+    }
+    lo[a] = l;
+    hi[a] = h;
+  }
+  return true;
+}
+
+void invalidate_graphs(lbm_ctx* c) {
+  for (int p = 0; p < 2; ++p)
+    if (c->graph[p]) {
+      (void)hipGraphExecDestroy(c->graph[p]);
+      c->graph[p] = nullptr;
+    }
+}
+
+void push_box_tiles(std::vector<BoxTile>& out, int region, const Region& r) {
+  const int64_t vol = (int64_t)(r.hi[0] - r.lo[0]) * (r.hi[1] - r.lo[1]) * (r.hi[2] - r.lo[2]);
+  for (int64_t s = 0; s < vol; s += 256) {
+    BoxTile t;
+    t.region = region;
+    t.count = (int)std::min<int64_t>(256, vol - s);
+    t.local0 = s;
+    out.push_back(t);
+  }
+}
+
+// Rebuilds regions, boundary and geometry work lists, and the stats buffer.
+lbm_status rebuild_work(lbm_ctx* c) {
+  c->regions.clear();
+  c->btiles.clear();
+  c->gtiles.clear();
+  c->bt_first.assign(c->n_inst, 0);
+  c->bt_count.assign(c->n_inst, 0);
+  c->time_dependent = false;
+  std::vector<int> geom_region(c->n_inst, -1);
+  for (int k = 0; k < c->n_inst; ++k) {
+    const lbm_instance_desc& d = c->desc[k];
+    const InstDev& I = c->hinst[k];
+    const int first = (int)c->regions.size();
+    const int n[3] = {d.nx, d.ny, d.nz};
+    for (int f = 0; f < 6; ++f) {
+      if (d.face[f] == LBM_FACE_PERIODIC) continue;
+      Region r;
+      r.inst = k;
+      r.first = first;
+      for (int a = 0; a < 3; ++a) {
+        r.lo[a] = 0;
+        r.hi[a] = n[a];
+      }
+      const int a = f / 2;
+      if (f % 2 == 0) r.hi[a] = 1; else r.lo[a] = n[a] - 1;
+      c->regions.push_back(r);
+    }
+    if (c->has_body[k]) {
+      Region r;
+      r.inst = k;
+      r.first = first;
+      for (int a = 0; a < 3; ++a) {
+        r.lo[a] = I.box_lo[a];
+        r.hi[a] = I.box_hi[a];
+      }
+      geom_region[k] = (int)c->regions.size();
+      c->regions.push_back(r);
+    }
+    if (d.ramp_steps > 0 && d.face[0] == LBM_FACE_INLET) c->time_dependent = true;
+    if (c->moving[k]) c->time_dependent = true;
+  }
+  for (int k = 0; k < c->n_inst; ++k) {
+    c->bt_first[k] = (int)c->btiles.size();
+    for (int r = 0; r < (int)c->regions.size(); ++r)
+      if (c->regions[r].inst == k) push_box_tiles(c->btiles, r, c->regions[r]);
+    c->bt_count[k] = (int)c->btiles.size() - c->bt_first[k];
+    if (c->moving[k] && geom_region[k] >= 0)
+      push_box_tiles(c->gtiles, geom_region[k], c->regions[geom_region[k]]);
+  }
+  lbm_status st;
+  if ((st = upload(c, &c->dregions, c->regions))) return st;
+  if ((st = upload(c, &c->dbtiles, c->btiles))) return st;
+  if ((st = upload(c, &c->dgtiles, c->gtiles))) return st;
+  const size_t need = c->tiles.size() + c->btiles.size() + 1;
+  if (need > c->dstats_cap) {
+    dev_free(c, c->dstats);
+    c->dstats = nullptr;
+    if ((st = dev_alloc(c, need * sizeof(StatPartial), (void**)&c->dstats))) return st;
+    c->dstats_cap = need;
+  }
+  invalidate_graphs(c);
+  return LBM_OK;
+}
+
+lbm_status rebuild_tiles(lbm_ctx* c) {
+  const int tsz = bulk_variant_tile(c->variant);
+  c->tiles.clear();
+  c->tile_first.assign(c->n_inst, 0);
+  c->tile_count.assign(c->n_inst, 0);
+  for (int k = 0; k < c->n_inst; ++k) {
+    c->tile_first[k] = (int)c->tiles.size();
+    const int64_t N = c->hinst[k].N;
+    for (int64_t s = 0; s < N; s += tsz) {
+      Tile t;
+      t.inst = k;
+      t.node0 = s;
+      t.count = (int)std::min<int64_t>(tsz, N - s);
+      c->tiles.push_back(t);
+    }
+    c->tile_count[k] = (int)c->tiles.size() - c->tile_first[k];
+  }
+  lbm_status st = upload(c, &c->dtiles, c->tiles);
+  if (st) return st;
+  const size_t need = c->tiles.size() + c->btiles.size() + 1;
+  if (need > c->dstats_cap) {
+    dev_free(c, c->dstats);
+    c->dstats = nullptr;
+    if ((st = dev_alloc(c, need * sizeof(StatPartial), (void**)&c->dstats))) return st;
+    c->dstats_cap = need;
+  }
+  invalidate_graphs(c);
+  return LBM_OK;
+}
+
+// Enqueues one step reading buf[src] and writing buf[1 - src].
+lbm_status enqueue_step(lbm_ctx* c, int src) {
+  StepBuffers b;
+  b.insts = c->dinst;
+  b.src = c->buf[src];
+  b.dst = c->buf[1 - src];
+  b.flags = c->flags;
+  b.err = c->derr;
+  b.clock = c->dclock;
+  b.stats = c->stats_enabled ? c->dstats : nullptr;
+  const int ngt = (int)c->gtiles.size();
+  if (ngt > 0)
+    for (int stage = 0; stage < 3; ++stage)
+      HIPCHECK(c, c->ops->geometry(stage, c->dinst, c->dregions, c->dgtiles, ngt, c->buf[src],
+                                   c->flags, c->dclock, 1, c->stream));
+  const int ntiles = (int)c->tiles.size();
+  const int nbt = (int)c->btiles.size();
+  if (c->launch_mode == 0) {
+    HIPCHECK(c, c->ops->boundary(b, c->dregions, c->dbtiles, 0, nbt, ntiles, c->stream));
+    HIPCHECK(c, c->ops->bulk(c->variant, b, c->dtiles, 0, ntiles, c->stream));
+  } else {
+    for (int k = 0; k < c->n_inst; ++k) {
+      HIPCHECK(c, c->ops->boundary(b, c->dregions, c->dbtiles, c->bt_first[k], c->bt_count[k],
+                                   ntiles + c->bt_first[k], c->stream));
+      HIPCHECK(c, c->ops->bulk(c->variant, b, c->dtiles, c->tile_first[k], c->tile_count[k],
+                               c->stream));
+    }
+  }
+  if (c->time_dependent) HIPCHECK(c, launch_tick(c->dclock, c->stream));
+  return LBM_OK;
+}
+
+lbm_status ensure_graph(lbm_ctx* c, int parity) {
+  if (c->graph[parity] || c->graph_failed) return LBM_OK;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    (void)hipGetLastError();
+    c->graph_failed = true;
+    return LBM_OK;
+  }
+  lbm_status s1 = enqueue_step(c, parity);
+  lbm_status s2 = s1 ? s1 : enqueue_step(c, 1 - parity);
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (s2 || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    c->graph_failed = true;
+    return s2;
+  }
+  e = hipGraphInstantiate(&c->graph[parity], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    c->graph[parity] = nullptr;
+    c->graph_failed = true;
+  }
+  return LBM_OK;
+}
+
+lbm_status check_error_word(lbm_ctx* c) {
+  uint32_t v = 0;
+  HIPCHECK(c, hipMemcpy(&v, c->derr, sizeof v, hipMemcpyDeviceToHost));
+  if (v) return fail(c, LBM_ERR_NONFINITE, "a node reached an invalid state (rho <= 0, |u| >= 1 or non-finite)");
+  return LBM_OK;
+}
+
+lbm_status check_inst(lbm_ctx* c, int inst) {
+  if (!c) return LBM_ERR_INVALID;
+  if (inst < 0 || inst >= c->n_inst) return fail(c, LBM_ERR_INVALID, "instance %d out of range", inst);
+  return LBM_OK;
+}
+
+// Runs the three geometry stages over the whole domain of instance k at the
+// current time (set-up of a new body).
+lbm_status full_geometry(lbm_ctx* c, int k) {
+  std::vector<Region> reg(1);
+  reg[0].inst = k;
+  reg[0].first = 0;
+  const lbm_instance_desc& d = c->desc[k];
+  const int n[3] = {d.nx, d.ny, d.nz};
+  for (int a = 0; a < 3; ++a) {
+    reg[0].lo[a] = 0;
+    reg[0].hi[a] = n[a];
+  }
+  std::vector<BoxTile> gt;
+  push_box_tiles(gt, 0, reg[0]);
+  Region* dr = nullptr;
+  BoxTile* dg = nullptr;
+  lbm_status st;
+  if ((st = upload(c, &dr, reg))) return st;
+  if ((st = upload(c, &dg, gt))) {
+    dev_free(c, dr);
+    return st;
+  }
+  for (int stage = 0; stage < 3 && !st; ++stage) {
+    hipError_t e = c->ops->geometry(stage, c->dinst, dr, dg, (int)gt.size(), c->buf[c->cur],
+                                    c->flags, c->dclock, 0, c->stream);
+    if (e != hipSuccess) st = fail(c, LBM_ERR_DEVICE, "geometry kernel: %s", hipGetErrorString(e));
+  }
+  hipError_t e = hipStreamSynchronize(c->stream);
+  dev_free(c, dr);
+  dev_free(c, dg);
+  if (!st && e != hipSuccess) st = fail(c, LBM_ERR_DEVICE, "geometry sync: %s", hipGetErrorString(e));
+  return st;
+}
+
+std::string cache_key(const lbm_ctx* c) {
+  hipDeviceProp_t prop;
+  std::string dev = "unknown";
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) dev = prop.gcnArchName;
+  for (auto& ch : dev)
+    if (ch == '"' || ch == ':' || ch == ' ') ch = '_';
+  std::ostringstream os;
+  os << "Q" << c->Q << "_S" << c->storage << "_I" << c->n_inst << "_N" << c->total_nodes;
+  if (c->n_inst == 1) os << "_" << c->desc[0].nx << "x" << c->desc[0].ny << "x" << c->desc[0].nz;
+  os << "_" << dev;
+  return os.str();
+}
+
+std::map<std::string, int> read_cache(const char* path) {
+  std::map<std::string, int> m;
+  if (!path) return m;
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    const size_t q0 = line.find('"');
+    if (q0 == std::string::npos) continue;
+    const size_t q1 = line.find('"', q0 + 1);
+    const size_t colon = line.find(':', q1);
+    if (q1 == std::string::npos || colon == std::string::npos) continue;
+    m[line.substr(q0 + 1, q1 - q0 - 1)] = std::atoi(line.c_str() + colon + 1);
+  }
+  return m;
+}
+
+void write_cache(const char* path, const std::map<std::string, int>& m) {
+  if (!path) return;
+  std::ofstream out(path);
+  out << "{\n";
+  size_t k = 0;
+  for (const auto& kv : m) out << "  \"" << kv.first << "\": " << kv.second << (++k < m.size() ? ",\n" : "\n");
+  out << "}\n";
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_status_string(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_ERR_INVALID: return "invalid argument";
+    case LBM_ERR_OOM: return "out of device memory";
+    case LBM_ERR_DEVICE: return "device error";
+    case LBM_ERR_NONFINITE: return "non-finite or invalid state";
+    case LBM_ERR_GEOMETRY: return "body does not fit the domain";
+    case LBM_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* lbm_last_error(const lbm_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+int lbm_variant_count(void) { return bulk_variant_count(); }
+const char* lbm_variant_name(int v) { return bulk_variant_name(v); }
+
+lbm_status lbm_destroy(lbm_ctx* c) {
+  if (!c) return LBM_OK;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  invalidate_graphs(c);
+  dev_free(c, c->buf[0]);
+  dev_free(c, c->buf[1]);
+  dev_free(c, c->flags);
+  dev_free(c, c->dinst);
+  dev_free(c, c->dclock);
+  dev_free(c, c->derr);
+  dev_free(c, c->dtiles);
+  dev_free(c, c->dregions);
+  dev_free(c, c->dbtiles);
+  dev_free(c, c->dgtiles);
+  dev_free(c, c->dstats);
+  if (c->herr) (void)hipHostFree(c->herr);
+  if (c->err_event) (void)hipEventDestroy(c->err_event);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_device_opts* opts,
+                      lbm_ctx** out) {
+  if (!out) return fail(nullptr, LBM_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!desc || n_instances < 1) return fail(nullptr, LBM_ERR_INVALID, "no instances");
+  const int Q = desc[0].lattice, storage = desc[0].storage;
+  for (int k = 0; k < n_instances; ++k) {
+    const lbm_instance_desc& d = desc[k];
+    if (d.lattice != LBM_D2Q9 && d.lattice != LBM_D3Q27)
+      return fail(nullptr, LBM_ERR_INVALID, "instance %d: unknown lattice %d", k, d.lattice);
+    if (d.lattice != Q || d.storage != storage)
+      return fail(nullptr, LBM_ERR_INVALID, "instance %d: lattice/storage differ from instance 0", k);
+    if (d.storage < LBM_F64 || d.storage > LBM_BF16_SHIFTED)
+      return fail(nullptr, LBM_ERR_INVALID, "instance %d: unknown storage %d", k, d.storage);
+    if (d.nx < 1 || d.ny < 1 || d.nz < 1 || (Q == 9 && d.nz != 1))
+      return fail(nullptr, LBM_ERR_INVALID, "instance %d: bad sizes %dx%dx%d", k, d.nx, d.ny, d.nz);
+    if ((int64_t)d.nx * d.ny * d.nz >= (int64_t(1) << 31))
+      return fail(nullptr, LBM_ERR_INVALID, "instance %d: more than 2^31 nodes", k);
+    if (!(d.nu > 0.0) || !std::isfinite(d.nu))
+      return fail(nullptr, LBM_ERR_INVALID, "instance %d: nu must be > 0", k);
+    if (d.collision != LBM_KBC && d.collision != LBM_LBGK)
+      return fail(nullptr, LBM_ERR_INVALID, "instance %d: unknown collision", k);
+    if (!valid_faces(d)) return fail(nullptr, LBM_ERR_INVALID, "instance %d: invalid faces", k);
+    if (d.inlet_profile != 0 && d.inlet_profile != 1)
+      return fail(nullptr, LBM_ERR_INVALID, "instance %d: unknown inlet profile", k);
+    if (d.ramp_steps < 0) return fail(nullptr, LBM_ERR_INVALID, "instance %d: ramp < 0", k);
+    for (int a = 0; a < 3; ++a)
+      if (!(std::fabs(d.u_in[a]) < 1.0)) return fail(nullptr, LBM_ERR_INVALID, "instance %d: |u_in| >= 1", k);
+  }
+  lbm_ctx* c = new lbm_ctx;
+  c->Q = Q;
+  c->D = Q == 27 ? 3 : 2;
+  c->storage = storage;
+  c->esize = storage_bytes(storage);
+  c->ops = get_ops(Q, storage);
+  c->n_inst = n_instances;
+  c->desc.assign(desc, desc + n_instances);
+  if (opts) {
+    c->device = opts->device;
+    c->ualloc = opts->alloc;
+    c->ufree = opts->free;
+    c->actx = opts->alloc_ctx;
+    c->use_graph = opts->use_graph;
+    if ((c->ualloc == nullptr) != (c->ufree == nullptr)) {
+      delete c;
+      return fail(nullptr, LBM_ERR_INVALID, "alloc and free callbacks must be given together");
+    }
+  }
+  lbm_status st = LBM_OK;
+  auto bail = [&](lbm_status s) {
+    g_create_error = c->err;
+    lbm_destroy(c);
+    return s;
+  };
+  if (hipSetDevice(c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(c, LBM_ERR_DEVICE, "hipSetDevice(%d) failed", c->device);
+    return bail(LBM_ERR_DEVICE);
+  }
+  if (opts && opts->hip_stream) {
+    c->stream = (hipStream_t)opts->hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      fail(c, LBM_ERR_DEVICE, "hipStreamCreate failed");
+      return bail(LBM_ERR_DEVICE);
+    }
+    c->own_stream = true;
+  }
+  // Layout: per instance Q population arrays of stride round_up(N, 64).
+  c->hinst.resize(n_instances);
+  c->moving.assign(n_instances, 0);
+  c->has_body.assign(n_instances, 0);
+  c->force_valid.assign(n_instances, 0);
+  size_t off = 0, foff = 0;
+  for (int k = 0; k < n_instances; ++k) {
+    const lbm_instance_desc& d = desc[k];
+    InstDev& I = c->hinst[k];
+    std::memset(&I, 0, sizeof I);
+    I.N = (int64_t)d.nx * d.ny * d.nz;
+    I.stride = (I.N + 63) / 64 * 64;
+    I.pop_off = (int64_t)off;
+    off += (size_t)Q * I.stride;
+    I.flag_off = needs_flags(d) ? (int64_t)foff : -1;
+    foff += (size_t)((I.N + 255) / 256 * 256);
+    I.nx = d.nx;
+    I.ny = d.ny;
+    I.nz = d.nz;
+    I.D = c->D;
+    I.divx = make_fastdiv((uint32_t)d.nx);
+    I.divy = make_fastdiv((uint32_t)d.ny);
+    I.beta = 1.0 / (6.0 * d.nu + 1.0);
+    I.beta_f = (float)I.beta;
+    I.collision = d.collision;
+    I.trace_in_s = d.kbc_trace_in_s ? 1 : 0;
+    I.inlet_profile = d.inlet_profile;
+    I.ramp_steps = d.ramp_steps;
+    I.body_kind = LBM_BODY_NONE;
+    for (int f = 0; f < 6; ++f) I.face[f] = d.face[f];
+    for (int a = 0; a < 3; ++a) I.u_in[a] = d.u_in[a];
+    c->total_nodes += I.N;
+  }
+  c->pop_elems = off;
+  c->flag_bytes = foff;
+  if ((st = dev_alloc(c, off * c->esize, &c->buf[0]))) return bail(st);
+  if ((st = dev_alloc(c, off * c->esize, &c->buf[1]))) return bail(st);
+  if ((st = dev_alloc(c, foff, (void**)&c->flags))) return bail(st);
+  if ((st = dev_alloc(c, sizeof(int64_t), (void**)&c->dclock))) return bail(st);
+  if ((st = dev_alloc(c, sizeof(uint32_t), (void**)&c->derr))) return bail(st);
+  if (hipHostMalloc((void**)&c->herr, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+    fail(c, LBM_ERR_OOM, "hipHostMalloc failed");
+    return bail(LBM_ERR_OOM);
+  }
+  *c->herr = 0;
+  if (hipEventCreateWithFlags(&c->err_event, hipEventDisableTiming) != hipSuccess) {
+    fail(c, LBM_ERR_DEVICE, "hipEventCreate failed");
+    return bail(LBM_ERR_DEVICE);
+  }
+  // Rest state: every deviation is zero in every storage format.
+  if (hipMemsetAsync(c->buf[0], 0, off * c->esize, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->buf[1], 0, off * c->esize, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->flags, 0, foff, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->dclock, 0, sizeof(int64_t), c->stream) != hipSuccess ||
+      hipMemsetAsync(c->derr, 0, sizeof(uint32_t), c->stream) != hipSuccess) {
+    fail(c, LBM_ERR_DEVICE, "hipMemsetAsync failed");
+    return bail(LBM_ERR_DEVICE);
+  }
+  // Static flags of non-periodic face planes.
+  for (int k = 0; k < n_instances; ++k) {
+    const InstDev& I = c->hinst[k];
+    if (I.flag_off < 0) continue;
+    const lbm_instance_desc& d = desc[k];
+    std::vector<uint8_t> h((size_t)I.N, 0);
+    for (int z = 0; z < d.nz; ++z)
+      for (int y = 0; y < d.ny; ++y)
+        for (int x = 0; x < d.nx; ++x) {
+          const int p[3] = {x, y, z}, n[3] = {d.nx, d.ny, d.nz};
+          bool on = false;
+          for (int a = 0; a < 3; ++a) {
+            if (p[a] == 0 && d.face[2 * a] != LBM_FACE_PERIODIC) on = true;
+            if (p[a] == n[a] - 1 && d.face[2 * a + 1] != LBM_FACE_PERIODIC) on = true;
+          }
+          if (on) h[(size_t)x + (size_t)d.nx * ((size_t)y + (size_t)d.ny * z)] = FLAG_STATIC;
+        }
+    if (hipMemcpy(c->flags + I.flag_off, h.data(), h.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      fail(c, LBM_ERR_DEVICE, "flag upload failed");
+      return bail(LBM_ERR_DEVICE);
+    }
+  }
+  if ((st = upload(c, &c->dinst, c->hinst))) return bail(st);
+  if ((st = rebuild_tiles(c))) return bail(st);
+  if ((st = rebuild_work(c))) return bail(st);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) {
+    fail(c, LBM_ERR_DEVICE, "initial synchronisation failed");
+    return bail(LBM_ERR_DEVICE);
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_init_fields(lbm_ctx* c, int inst, const double* rho, const double* u) {
+  lbm_status st = check_inst(c, inst);
+  if (st) return st;
+  if (!rho || !u) return fail(c, LBM_ERR_INVALID, "rho and u are required");
+  const InstDev& I = c->hinst[inst];
+  const int64_t N = I.N;
+  for (int64_t n = 0; n < N; ++n) {
+    if (!(rho[n] > 0.0) || !std::isfinite(rho[n])) return fail(c, LBM_ERR_INVALID, "rho <= 0 at node %lld", (long long)n);
+    for (int a = 0; a < c->D; ++a)
+      if (!(std::fabs(u[a * N + n]) < 1.0)) return fail(c, LBM_ERR_INVALID, "|u| >= 1 at node %lld", (long long)n);
+  }
+  double *dr = nullptr, *du = nullptr;
+  if ((st = dev_alloc(c, N * sizeof(double), (void**)&dr))) return st;
+  if ((st = dev_alloc(c, c->D * N * sizeof(double), (void**)&du))) {
+    dev_free(c, dr);
+    return st;
+  }
+  hipError_t e = hipMemcpyAsync(dr, rho, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(du, u, c->D * N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = c->ops->init_eq(c->dinst, inst, N, dr, du, c->buf[c->cur], c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_free(c, dr);
+  dev_free(c, du);
+  if (e != hipSuccess) return fail(c, LBM_ERR_DEVICE, "init_fields: %s", hipGetErrorString(e));
+  c->force_valid[inst] = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_geometry(lbm_ctx* c, int inst, const lbm_body* body) {
+  lbm_status st = check_inst(c, inst);
+  if (st) return st;
+  lbm_body b;
+  std::memset(&b, 0, sizeof b);
+  if (body) b = *body;
+  if (b.kind < LBM_BODY_NONE || b.kind > LBM_BODY_PLATES)
+    return fail(c, LBM_ERR_INVALID, "unknown body kind %d", b.kind);
+  if (b.kind == LBM_BODY_FLAP && c->D != 2) return fail(c, LBM_ERR_INVALID, "flap bodies are 2D only");
+  for (int k = 0; k < 16; ++k)
+    if (!std::isfinite(b.params[k])) return fail(c, LBM_ERR_INVALID, "non-finite body parameter");
+  if (b.kind == LBM_BODY_SPHERE && !(b.params[3] > 0.0)) return fail(c, LBM_ERR_INVALID, "radius must be > 0");
+  if (b.kind == LBM_BODY_FLAP && !(b.params[1] > 0.0 && b.params[2] > 0.0))
+    return fail(c, LBM_ERR_INVALID, "flap length and thickness must be > 0");
+  InstDev& I = c->hinst[inst];
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  if (b.kind != LBM_BODY_NONE && !body_box(c, inst, b, lo, hi))
+    return fail(c, LBM_ERR_GEOMETRY, "the body's swept region crosses a periodic face");
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  if (I.flag_off < 0) {
+    // Instance had no flags yet: its slice of the pool is zero already.
+    int64_t foff = 0;
+    for (int k = 0; k < inst; ++k) foff += (c->hinst[k].N + 255) / 256 * 256;
+    I.flag_off = foff;
+  }
+  I.body_kind = b.kind;
+  for (int k = 0; k < 16; ++k) I.body[k] = b.params[k];
+  for (int a = 0; a < 3; ++a) {
+    I.box_lo[a] = lo[a];
+    I.box_hi[a] = hi[a];
+  }
+  const double* p = b.params;
+  c->has_body[inst] = b.kind != LBM_BODY_NONE;
+  c->moving[inst] = (b.kind == LBM_BODY_SPHERE && p[7] != 0.0 && (p[4] != 0.0 || p[5] != 0.0 || p[6] != 0.0)) ||
+                    (b.kind == LBM_BODY_FLAP && p[4] != 0.0 && p[3] != 0.0);
+  if ((st = upload(c, &c->dinst, c->hinst))) return st;
+  HIPCHECK(c, hipMemcpy(c->dclock, &c->step, sizeof(int64_t), hipMemcpyHostToDevice));
+  if ((st = full_geometry(c, inst))) return st;
+  if ((st = rebuild_work(c))) return st;
+  c->force_valid[inst] = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int n_steps) {
+  if (!c) return LBM_ERR_INVALID;
+  if (n_steps < 0) return fail(c, LBM_ERR_INVALID, "n_steps < 0");
+  if (c->err_pending && hipEventQuery(c->err_event) == hipSuccess) {
+    c->err_pending = false;
+    if (*c->herr) return fail(c, LBM_ERR_NONFINITE, "a node reached an invalid state");
+  }
+  lbm_status st;
+  int n = n_steps;
+  while (n > 0) {
+    if (c->use_graph && n >= 2 && !c->graph_failed) {
+      if ((st = ensure_graph(c, c->cur))) return st;
+      if (c->graph[c->cur]) {
+        HIPCHECK(c, hipGraphLaunch(c->graph[c->cur], c->stream));
+        n -= 2;
+        c->step += 2;
+        continue;
+      }
+    }
+    if ((st = enqueue_step(c, c->cur))) return st;
+    c->cur ^= 1;
+    c->step += 1;
+    n -= 1;
+  }
+  if (n_steps > 0) {
+    for (int k = 0; k < c->n_inst; ++k) c->force_valid[k] = 1;
+    if (!c->err_pending) {
+      HIPCHECK(c, hipMemcpyAsync(c->herr, c->derr, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+      HIPCHECK(c, hipEventRecord(c->err_event, c->stream));
+      c->err_pending = true;
+    }
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_synchronize(lbm_ctx* c) {
+  if (!c) return LBM_ERR_INVALID;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  return check_error_word(c);
+}
+
+lbm_status lbm_moments(lbm_ctx* c, int inst, double* rho, double* u, lbm_totals* tot) {
+  lbm_status st = check_inst(c, inst);
+  if (st) return st;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  const InstDev& I = c->hinst[inst];
+  const int64_t N = I.N;
+  double *dr = nullptr, *du = nullptr, *dp = nullptr, *dout = nullptr;
+  const int64_t nparts_max = (N + 255) / 256;
+  if ((st = dev_alloc(c, N * sizeof(double), (void**)&dr))) return st;
+  if ((st = dev_alloc(c, c->D * N * sizeof(double), (void**)&du))) { dev_free(c, dr); return st; }
+  if ((st = dev_alloc(c, nparts_max * 4 * sizeof(double) + 64 * sizeof(double), (void**)&dp))) {
+    dev_free(c, dr); dev_free(c, du); return st;
+  }
+  dout = dp + nparts_max * 4;
+  int np = 0;
+  hipError_t e = c->ops->moments(c->dinst, inst, N, c->buf[c->cur], c->flags, dr, du, dp, &np, c->stream);
+  if (e == hipSuccess) e = launch_reduce(dp, np, 4, dout, c->stream);
+  double sums[4] = {0, 0, 0, 0};
+  StatPartial sp[2];
+  bool have_stats = false;
+  if (e == hipSuccess && tot && c->stats_enabled && c->step > 0) {
+    StatPartial* so = reinterpret_cast<StatPartial*>(dout + 8);
+    e = launch_reduce_stats(c->dstats + c->tile_first[inst], c->tile_count[inst], so, c->stream);
+    if (e == hipSuccess)
+      e = launch_reduce_stats(c->dstats + c->tiles.size() + c->bt_first[inst], c->bt_count[inst], so + 1, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(sp, so, sizeof sp, hipMemcpyDeviceToHost, c->stream);
+    have_stats = true;
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(sums, dout, sizeof sums, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, dr, N * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && u) e = hipMemcpyAsync(u, du, c->D * N * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_free(c, dr);
+  dev_free(c, du);
+  dev_free(c, dp);
+  if (e != hipSuccess) return fail(c, LBM_ERR_DEVICE, "moments: %s", hipGetErrorString(e));
+  if (tot) {
+    std::memset(tot, 0, sizeof *tot);
+    tot->mass = sums[0];
+    for (int a = 0; a < 3; ++a) tot->momentum[a] = sums[1 + a];
+    tot->gamma_min = tot->gamma_mean = tot->gamma_max = 2.0;
+    if (have_stats) {
+      const uint64_t cnt = (uint64_t)sp[0].count + sp[1].count;
+      if (cnt) {
+        tot->gamma_min = std::min(sp[0].count ? sp[0].gmin : 1e30f, sp[1].count ? sp[1].gmin : 1e30f);
+        tot->gamma_max = std::max(sp[0].count ? sp[0].gmax : -1e30f, sp[1].count ? sp[1].gmax : -1e30f);
+        tot->gamma_mean = (sp[0].gsum + sp[1].gsum) / (double)cnt;
+        tot->fp64_gamma_fraction = (double)(sp[0].fp64 + sp[1].fp64) / (double)cnt;
+      }
+    }
+    tot->step = c->step;
+  }
+  return check_error_word(c);
+}
+
+lbm_status lbm_wall_force(lbm_ctx* c, int inst, const double* xq, const double* nq,
+                          const double* wq, int n_q, double* traction, double force[3]) {
+  lbm_status st = check_inst(c, inst);
+  if (st) return st;
+  if (!force || n_q < 0 || (n_q > 0 && (!xq || !nq || !wq)))
+    return fail(c, LBM_ERR_INVALID, "bad quadrature arguments");
+  if (!c->force_valid[inst])
+    return fail(c, LBM_ERR_INVALID, "wall force needs a step after the last geometry or state change");
+  force[0] = force[1] = force[2] = 0.0;
+  if (n_q == 0) return LBM_OK;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  const int D = c->D;
+  const int np_max = (n_q + 255) / 256;
+  double* dm = nullptr;
+  const size_t nd = (size_t)n_q * D * 3 + n_q + (size_t)np_max * 4 + 8;
+  if ((st = dev_alloc(c, nd * sizeof(double), (void**)&dm))) return st;
+  double *dx = dm, *dn = dx + (size_t)n_q * D, *dw = dn + (size_t)n_q * D, *dt = dw + n_q;
+  double *dp = dt + (size_t)n_q * D, *dout = dp + (size_t)np_max * 4;
+  int np = 0;
+  double sums[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(dx, xq, (size_t)n_q * D * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(dn, nq, (size_t)n_q * D * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(dw, wq, (size_t)n_q * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = c->ops->force(c->dinst, inst, c->buf[1 - c->cur], c->flags, c->dclock, dx, dn, dw, n_q, dt,
+                      dp, &np, c->stream);
+  if (e == hipSuccess) e = launch_reduce(dp, np, 4, dout, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(sums, dout, sizeof sums, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && traction)
+    e = hipMemcpyAsync(traction, dt, (size_t)n_q * D * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_free(c, dm);
+  if (e != hipSuccess) return fail(c, LBM_ERR_DEVICE, "wall force: %s", hipGetErrorString(e));
+  for (int a = 0; a < D; ++a) force[a] = sums[a];
+  if (sums[3] != 0.0) return fail(c, LBM_ERR_GEOMETRY, "%d quadrature points found no fluid node near a probe", (int)sums[3]);
+  return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, int inst, double* f) {
+  lbm_status st = check_inst(c, inst);
+  if (st) return st;
+  if (!f) return fail(c, LBM_ERR_INVALID, "f is NULL");
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  const int64_t N = c->hinst[inst].N;
+  double* df = nullptr;
+  if ((st = dev_alloc(c, (size_t)c->Q * N * sizeof(double), (void**)&df))) return st;
+  hipError_t e = c->ops->decode(c->dinst, inst, N, c->buf[c->cur], df, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(f, df, (size_t)c->Q * N * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_free(c, df);
+  if (e != hipSuccess) return fail(c, LBM_ERR_DEVICE, "get_populations: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_ctx* c, int inst, const double* f) {
+  lbm_status st = check_inst(c, inst);
+  if (st) return st;
+  if (!f) return fail(c, LBM_ERR_INVALID, "f is NULL");
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  const int64_t N = c->hinst[inst].N;
+  double* df = nullptr;
+  if ((st = dev_alloc(c, (size_t)c->Q * N * sizeof(double), (void**)&df))) return st;
+  hipError_t e = hipMemcpyAsync(df, f, (size_t)c->Q * N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = c->ops->encode(c->dinst, inst, N, df, c->buf[c->cur], c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_free(c, df);
+  if (e != hipSuccess) return fail(c, LBM_ERR_DEVICE, "set_populations: %s", hipGetErrorString(e));
+  c->force_valid[inst] = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_stats(lbm_ctx* c, int enabled) {
+  if (!c) return LBM_ERR_INVALID;
+  if ((enabled != 0) != (c->stats_enabled != 0)) invalidate_graphs(c);
+  c->stats_enabled = enabled != 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_launch_mode(lbm_ctx* c, int mode) {
+  if (!c) return LBM_ERR_INVALID;
+  if (mode != 0 && mode != 1) return fail(c, LBM_ERR_INVALID, "launch mode must be 0 or 1");
+  if (mode != c->launch_mode) invalidate_graphs(c);
+  c->launch_mode = mode;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_variant(lbm_ctx* c, int v) {
+  if (!c) return LBM_ERR_INVALID;
+  if (v < 0 || v >= bulk_variant_count()) return fail(c, LBM_ERR_INVALID, "variant %d out of range", v);
+  if (v == c->variant) return LBM_OK;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  c->variant = v;
+  return rebuild_tiles(c);
+}
+
+lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int* chosen) {
+  if (!c) return LBM_ERR_INVALID;
+  const std::string key = cache_key(c);
+  std::map<std::string, int> cache = read_cache(cache_path);
+  auto it = cache.find(key);
+  lbm_status st;
+  if (it != cache.end() && it->second >= 0 && it->second < bulk_variant_count()) {
+    if ((st = lbm_set_variant(c, it->second))) return st;
+    if (chosen) *chosen = c->variant;
+    return LBM_OK;
+  }
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  // Save state, flags and clock; the trial steps are undone afterwards.
+  const size_t pbytes = c->pop_elems * c->esize;
+  void* save = nullptr;
+  uint8_t* fsave = nullptr;
+  if ((st = dev_alloc(c, pbytes, &save))) return st;
+  if ((st = dev_alloc(c, c->flag_bytes, (void**)&fsave))) { dev_free(c, save); return st; }
+  HIPCHECK(c, hipMemcpyAsync(save, c->buf[c->cur], pbytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHECK(c, hipMemcpyAsync(fsave, c->flags, c->flag_bytes, hipMemcpyDeviceToDevice, c->stream));
+  const int cur0 = c->cur;
+  const int64_t step0 = c->step;
+  hipEvent_t e0, e1;
+  HIPCHECK(c, hipEventCreate(&e0));
+  HIPCHECK(c, hipEventCreate(&e1));
+  int best = c->variant;
+  float best_ms = 1e30f;
+  for (int v = 0; v < bulk_variant_count(); ++v) {
+    if ((st = lbm_set_variant(c, v))) break;
+    if ((st = lbm_step(c, 2))) break;
+    HIPCHECK(c, hipEventRecord(e0, c->stream));
+    if ((st = lbm_step(c, 6))) break;
+    HIPCHECK(c, hipEventRecord(e1, c->stream));
+    HIPCHECK(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHECK(c, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHECK(c, hipMemcpyAsync(c->buf[cur0], save, pbytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHECK(c, hipMemcpyAsync(c->flags, fsave, c->flag_bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHECK(c, hipMemcpyAsync(c->dclock, &step0, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  HIPCHECK(c, hipMemsetAsync(c->derr, 0, sizeof(uint32_t), c->stream));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  dev_free(c, save);
+  dev_free(c, fsave);
+  c->cur = cur0;
+  c->step = step0;
+  c->err_pending = false;
+  for (int k = 0; k < c->n_inst; ++k) c->force_valid[k] = 0;
+  if (st) return st;
+  if ((st = lbm_set_variant(c, best))) return st;
+  cache[key] = best;
+  write_cache(cache_path, cache);
+  if (chosen) *chosen = best;
+  return LBM_OK;
+}
+
+lbm_status lbm_info(const lbm_ctx* c, int inst, int64_t* nodes, int64_t* total_nodes,
+                    int* bytes_per_update, int64_t* step) {
+  if (!c) return LBM_ERR_INVALID;
+  if (inst < 0 || inst >= c->n_inst) return LBM_ERR_INVALID;
+  if (nodes) *nodes = c->hinst[inst].N;
+  if (total_nodes) *total_nodes = c->total_nodes;
+  if (bytes_per_update) *bytes_per_update = 2 * c->Q * c->esize;
+  if (step) *step = c->step;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,373 @@
+// Per-node arithmetic of the KBC step in deviation form.
+//
+// The state of a node is the deviation d_i = f_i - W_i.  The arithmetic keeps
+// every quantity as a deviation from the rest state so that FP32 does not lose
+// the O(u) information against the O(1) weights:
+//   rho~ = sum d_i, j = sum c_i d_i, rho = 1 + rho~, u = j / rho;
+//   f^eq_i - W_i = W_i (rho~ + rho E_i), E_i = prod_a (1 + e_a(c_ia)) - 1,
+// where e_a(c) are the per-axis deviations of the entropic equilibrium
+// f^eq_i = rho W_i prod_a (2 - s_a) x_a^{c_ia}, s_a = sqrt(1 + 3 u_a^2),
+// x_a = (2 u_a + s_a)/(1 - u_a)  (minimiser of H under mass and momentum,
+// Sec. II.A Eqs. 4-5):
+//   sigma = 3u^2/(1+s) (= s - 1),  e(0) = -sigma,
+//   X = (3u + sigma)/(1 - u) (= x - 1),  e(+1) = X - sigma - sigma X,
+//   Y = -(3u + sigma)/(2u + s) (= 1/x - 1),  e(-1) = Y - sigma - sigma Y.
+#pragma once
+
+#include "lbm_device.hpp"
+
+namespace kbc {
+
+template <typename R>
+struct AxisEq {
+  R e0, ep, em;   // equilibrium factor deviations for c = 0, +1, -1
+  R g0, gp, gm;   // 1 / (w(c) (1 + e(c)))
+};
+
+template <typename R>
+__device__ __forceinline__ AxisEq<R> axis_eq(R u) {
+  AxisEq<R> A;
+  const R uu = u * u;
+  const R s = fsqrt(R(1) + R(3) * uu);
+  const R sig = R(3) * uu * frcp(R(1) + s);
+  const R t = R(3) * u + sig;
+  const R X = t * frcp(R(1) - u);
+  const R Y = -t * frcp(R(2) * u + s);
+  A.e0 = -sig;
+  A.ep = X - sig - sig * X;
+  A.em = Y - sig - sig * Y;
+  const R iz = frcp(R(1) - sig);   // 1 / (2 - s)
+  A.g0 = R(1.5) * iz;
+  A.gp = R(6) * iz * (R(1) + Y);
+  A.gm = R(6) * iz * (R(1) + X);
+  return A;
+}
+
+template <typename R>
+__device__ __forceinline__ R sel_e(const AxisEq<R>& A, int c) {
+  return c == 0 ? A.e0 : (c > 0 ? A.ep : A.em);
+}
+template <typename R>
+__device__ __forceinline__ R sel_g(const AxisEq<R>& A, int c) {
+  return c == 0 ? A.g0 : (c > 0 ? A.gp : A.gm);
+}
+
+// E_i for population i from the per-axis deviations (accumulated as
+// E <- E + e + E e, exact in exact arithmetic).
+template <int Q, typename R>
+__device__ __forceinline__ R eq_E(const AxisEq<R> (&A)[3], int i) {
+  R E = sel_e(A[0], cx(i));
+  {
+    const R e = sel_e(A[1], cy(i));
+    E = E + e + E * e;
+  }
+  if (Q == 27) {
+    const R e = sel_e(A[2], cz<Q>(i));
+    E = E + e + E * e;
+  }
+  return E;
+}
+
+// Equilibrium deviations f^eq_i - W_i for given rho~ = rho - 1 and u.
+template <int Q, typename R>
+__device__ __forceinline__ void feq_dev(R rt, const R (&u)[3], R (&out)[Q]) {
+  AxisEq<R> A[3];
+#pragma unroll
+  for (int a = 0; a < dims<Q>(); ++a) A[a] = axis_eq(u[a]);
+  if (dims<Q>() == 2) A[2] = A[1];   // unused in 2D
+  const R rho = R(1) + rt;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) out[i] = R(weight<Q>(i)) * (rt + rho * eq_E<Q>(A, i));
+}
+
+// Moments of a deviation state.
+template <int Q, typename R>
+__device__ __forceinline__ void moments_dev(const R (&d)[Q], R& rt, R (&j)[3]) {
+  rt = R(0);
+  j[0] = j[1] = j[2] = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    rt += d[i];
+    if (cx(i) > 0) j[0] += d[i];
+    if (cx(i) < 0) j[0] -= d[i];
+    if (cy(i) > 0) j[1] += d[i];
+    if (cy(i) < 0) j[1] -= d[i];
+    if (cz<Q>(i) > 0) j[2] += d[i];
+    if (cz<Q>(i) < 0) j[2] -= d[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Shear part of Delta = f - f^eq (Sec. II.A, Eqs. 2-3) in the natural moment
+// basis: the deviatoric second-order moments.  With P = sum Delta c c,
+// T = tr P and Dev = P - T/D I:
+//   Delta s_i = Dev_aa / 2            if c_i = +-e_a,
+//   Delta s_i = c_ia c_ib P_ab / 4    if c_i has exactly two non-zero a != b,
+//   Delta s_i = 0                     otherwise;
+// with the trace moved into s: rest -T, faces +T/(2D).
+// ---------------------------------------------------------------------------
+template <int Q, typename R>
+struct Shear {
+  R Dxx, Dyy, Dzz, Pxy, Pxz, Pyz, T;
+};
+
+template <int Q, typename R>
+__device__ __forceinline__ Shear<Q, R> shear_moments(const R (&delta)[Q]) {
+  R Pxx = R(0), Pyy = R(0), Pzz = R(0), Pxy = R(0), Pxz = R(0), Pyz = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R v = delta[i];
+    if (cx(i) != 0) Pxx += v;
+    if (cy(i) != 0) Pyy += v;
+    if (cz<Q>(i) != 0) Pzz += v;
+    if (cx(i) * cy(i) > 0) Pxy += v;
+    if (cx(i) * cy(i) < 0) Pxy -= v;
+    if (cx(i) * cz<Q>(i) > 0) Pxz += v;
+    if (cx(i) * cz<Q>(i) < 0) Pxz -= v;
+    if (cy(i) * cz<Q>(i) > 0) Pyz += v;
+    if (cy(i) * cz<Q>(i) < 0) Pyz -= v;
+  }
+  Shear<Q, R> S;
+  S.Pxy = Pxy;
+  S.Pxz = Pxz;
+  S.Pyz = Pyz;
+  if (Q == 27) {
+    S.T = Pxx + Pyy + Pzz;
+    const R t3 = S.T * R(1.0 / 3.0);
+    S.Dxx = Pxx - t3;
+    S.Dyy = Pyy - t3;
+    S.Dzz = -(S.Dxx + S.Dyy);   // trace exactly zero
+  } else {
+    S.T = Pxx + Pyy;
+    S.Dxx = R(0.5) * (Pxx - Pyy);
+    S.Dyy = -S.Dxx;
+    S.Dzz = R(0);
+  }
+  return S;
+}
+
+template <int Q, typename R>
+__device__ __forceinline__ R shear_pop(const Shear<Q, R>& S, int i, R ts) {
+  const int n = nnz<Q>(i);
+  if (n == 1) {
+    const R dev = cx(i) != 0 ? S.Dxx : (cy(i) != 0 ? S.Dyy : S.Dzz);
+    return R(0.5) * dev + ts * R(0.5 / dims<Q>());
+  }
+  if (n == 2) {
+    const R p = (cx(i) != 0 && cy(i) != 0) ? S.Pxy : ((cx(i) != 0) ? S.Pxz : S.Pyz);
+    const int sgn = (cx(i) != 0 && cy(i) != 0) ? cx(i) * cy(i)
+                    : (cx(i) != 0 ? cx(i) * cz<Q>(i) : cy(i) * cz<Q>(i));
+    return sgn > 0 ? R(0.25) * p : R(-0.25) * p;
+  }
+  if (n == 0) return -ts;
+  return R(0);
+}
+
+// Removes the mass and momentum that rounding left in Delta h: in exact
+// arithmetic sum dh = sum c dh = 0; the correction uses the rest and axis
+// populations (columns of the inverse moment basis for rho and j).
+template <int Q, typename R>
+__device__ __forceinline__ void project_conserved(R (&dh)[Q]) {
+  R m = R(0), J[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    m += dh[i];
+    if (cx(i) > 0) J[0] += dh[i];
+    if (cx(i) < 0) J[0] -= dh[i];
+    if (cy(i) > 0) J[1] += dh[i];
+    if (cy(i) < 0) J[1] -= dh[i];
+    if (cz<Q>(i) > 0) J[2] += dh[i];
+    if (cz<Q>(i) < 0) J[2] -= dh[i];
+  }
+  dh[rest<Q>()] -= m;
+#pragma unroll
+  for (int a = 0; a < dims<Q>(); ++a) {
+    dh[axis_pop<Q>(a, +1)] -= R(0.5) * J[a];
+    dh[axis_pop<Q>(a, -1)] += R(0.5) * J[a];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gamma in FP64 for near-equilibrium nodes of the FP32 paths.  Streams over
+// the populations several times instead of holding FP64 arrays, so that the
+// rarely taken branch does not raise the register budget of the kernel.
+// ---------------------------------------------------------------------------
+template <int Q>
+__device__ __noinline__ double gamma_fp64(const float (&d)[Q], double beta, int trace_in_s) {
+  double rt = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double v = d[i];
+    rt += v;
+    j[0] += cx(i) * v;
+    j[1] += cy(i) * v;
+    j[2] += cz<Q>(i) * v;
+  }
+  const double rho = 1.0 + rt, ir = 1.0 / rho;
+  AxisEq<double> A[3];
+#pragma unroll
+  for (int a = 0; a < dims<Q>(); ++a) A[a] = axis_eq(j[a] * ir);
+  if (dims<Q>() == 2) A[2] = A[1];   // unused in 2D
+  // Pass 1: second moments of Delta.
+  double P[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double dl = (double)d[i] - weight<Q>(i) * (rt + rho * eq_E<Q>(A, i));
+    P[0] += cx(i) * cx(i) * dl;
+    P[1] += cy(i) * cy(i) * dl;
+    P[2] += cz<Q>(i) * cz<Q>(i) * dl;
+    P[3] += cx(i) * cy(i) * dl;
+    P[4] += cx(i) * cz<Q>(i) * dl;
+    P[5] += cy(i) * cz<Q>(i) * dl;
+  }
+  Shear<Q, double> S;
+  S.Pxy = P[3];
+  S.Pxz = P[4];
+  S.Pyz = P[5];
+  if (Q == 27) {
+    S.T = P[0] + P[1] + P[2];
+    S.Dxx = P[0] - S.T / 3.0;
+    S.Dyy = P[1] - S.T / 3.0;
+    S.Dzz = -(S.Dxx + S.Dyy);
+  } else {
+    S.T = P[0] + P[1];
+    S.Dxx = 0.5 * (P[0] - P[1]);
+    S.Dyy = -S.Dxx;
+    S.Dzz = 0.0;
+  }
+  const double ts = trace_in_s ? S.T : 0.0;
+  // Pass 2: mass and momentum left in Delta h by rounding.
+  double m = 0.0, J[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double dl = (double)d[i] - weight<Q>(i) * (rt + rho * eq_E<Q>(A, i));
+    const double h = dl - shear_pop<Q>(S, i, ts);
+    m += h;
+    J[0] += cx(i) * h;
+    J[1] += cy(i) * h;
+    J[2] += cz<Q>(i) * h;
+  }
+  // Pass 3: the two scalar products with weight 1/f^eq.
+  double a = 0.0, b = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double dl = (double)d[i] - weight<Q>(i) * (rt + rho * eq_E<Q>(A, i));
+    const double s = shear_pop<Q>(S, i, ts);
+    double h = dl - s;
+    if (i == rest<Q>()) h -= m;
+#pragma unroll
+    for (int ax = 0; ax < dims<Q>(); ++ax) {
+      if (i == axis_pop<Q>(ax, +1)) h -= 0.5 * J[ax];
+      if (i == axis_pop<Q>(ax, -1)) h += 0.5 * J[ax];
+    }
+    double inv = ir * sel_g(A[0], cx(i)) * sel_g(A[1], cy(i));
+    if (Q == 27) inv *= sel_g(A[2], cz<Q>(i));
+    a += s * h * inv;
+    b += h * h * inv;
+  }
+  if (!(b > 0.0)) return 2.0;
+  return 1.0 / beta - (2.0 - 1.0 / beta) * a / b;
+}
+
+// Threshold on <Delta|Delta> below which the FP32 paths take gamma from FP64.
+constexpr float kNearEq = 1e-10f;
+
+struct CollideOut {
+  float gamma;
+  int fp64;
+};
+
+// ---------------------------------------------------------------------------
+// KBC collision of one node in place (Sec. II.A, Eqs. 1, 3, 6):
+//   f' = f - beta (2 Delta s + gamma Delta h),
+//   gamma = 1/beta - (2 - 1/beta) <Ds|Dh> / <Dh|Dh>, <X|Y> = sum X_i Y_i / f^eq_i,
+// gamma = 2 when <Dh|Dh> = 0 and in LBGK mode.  Returns false (state left
+// unchanged) if rho <= 0, |u_a| >= 1 or the state is not finite.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct CollideParams {
+  R beta, inv_beta;
+  double beta_d;
+  int lbgk, trace_in_s;
+};
+
+template <int Q, typename R>
+__device__ __forceinline__ bool collide(R (&d)[Q], const CollideParams<R>& P, CollideOut& out) {
+  constexpr int D = dims<Q>();
+  R rt, j[3];
+  moments_dev<Q>(d, rt, j);
+  const R rho = R(1) + rt;
+  const R ir = frcp(rho);
+  R u[3] = {j[0] * ir, j[1] * ir, D == 3 ? j[2] * ir : R(0)};
+  const bool ok = rho > R(0) && u[0] < R(1) && u[0] > R(-1) && u[1] < R(1) && u[1] > R(-1) &&
+                  u[2] < R(1) && u[2] > R(-1);
+  if (!ok) {
+    out.gamma = 2.0f;
+    out.fp64 = 0;
+    return false;
+  }
+  AxisEq<R> A[3];
+#pragma unroll
+  for (int a = 0; a < D; ++a) A[a] = axis_eq(u[a]);
+  if (D == 2) A[2] = A[1];   // unused in 2D
+
+  R dh[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) dh[i] = d[i] - R(weight<Q>(i)) * (rt + rho * eq_E<Q>(A, i));
+  const Shear<Q, R> S = shear_moments<Q>(dh);
+  const R ts = P.trace_in_s ? S.T : R(0);
+  R ds[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    ds[i] = shear_pop<Q>(S, i, ts);
+    dh[i] -= ds[i];
+  }
+  project_conserved<Q>(dh);
+
+  R gamma = R(2);
+  out.fp64 = 0;
+  if (!P.lbgk) {
+    R a = R(0), b = R(0), ss = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      R inv = ir * sel_g(A[0], cx(i)) * sel_g(A[1], cy(i));
+      if (Q == 27) inv *= sel_g(A[2], cz<Q>(i));
+      const R hi = dh[i] * inv;
+      b += hi * dh[i];
+      a += hi * ds[i];
+      ss += ds[i] * ds[i] * inv;
+    }
+    const R dd = ss + R(2) * a + b;   // <Delta|Delta>
+    if (sizeof(R) == 4 && dd < R(kNearEq)) {
+      float tmp[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) tmp[i] = (float)d[i];
+      gamma = (R)gamma_fp64<Q>(tmp, P.beta_d, P.trace_in_s);
+      out.fp64 = 1;
+    } else if (b > R(0)) {
+      gamma = P.inv_beta - (R(2) - P.inv_beta) * a * frcp(b);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) d[i] -= P.beta * (R(2) * ds[i] + gamma * dh[i]);
+  out.gamma = (float)gamma;
+  return true;
+}
+
+// Grad's approximation (Sec. II.C.1) as a deviation from W_i, cs^2 = 1/3:
+//   f*_i - W_i = W_i [ rho - 1 + 3 rho c.v + (9/2)(Pi - rho/3 I):(c c - I/3) ].
+// Pi is given as (xx, yy, zz, xy, xz, yz).
+template <int Q, typename R>
+__device__ __forceinline__ R grad_dev(int i, R rho, const R (&v)[3], const R (&Pi)[6]) {
+  const R c0 = R(cx(i)), c1 = R(cy(i)), c2 = R(cz<Q>(i));
+  const R third = R(1.0 / 3.0);
+  const R cv = c0 * v[0] + c1 * v[1] + c2 * v[2];
+  const R r3 = rho * third;
+  R contr = (Pi[0] - r3) * (c0 * c0 - third) + (Pi[1] - r3) * (c1 * c1 - third) +
+            R(2) * Pi[3] * c0 * c1;
+  if (Q == 27)
+    contr += (Pi[2] - r3) * (c2 * c2 - third) + R(2) * Pi[4] * c0 * c2 + R(2) * Pi[5] * c1 * c2;
+  return R(weight<Q>(i)) * (rho - R(1) + R(3) * rho * cv + R(4.5) * contr);
+}
+
+}  // namespace kbc

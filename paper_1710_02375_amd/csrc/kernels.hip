@@ -1,0 +1,1033 @@
+// Device kernels of the KBC lattice Boltzmann step for gfx950.
+//
+//   bulk      fused pull-stream + KBC collide for every node without a special
+//             flag: the hot kernel, one thread per node, SoA populations.
+//   boundary  nodes on non-periodic faces and nodes with cut links: pull,
+//             Grad's approximation for the missing populations, inflow /
+//             outflow conditions, then the same collision.
+//   geometry  prescribed body motion on the device (solid marks at the next
+//             time, fresh-node refill, cut-link marks).
+//   init / decode / encode / moments / force / reductions.
+#include <math.h>
+
+#include "kbc_node.hpp"
+#include "kernels.hpp"
+
+namespace kbc {
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+struct Coord {
+  int x, y, z;
+};
+
+__device__ __forceinline__ Coord node_coord(const InstDev& I, uint32_t node) {
+  const uint32_t row = fdiv_u32(node, I.divx);
+  const uint32_t z = fdiv_u32(row, I.divy);
+  Coord c;
+  c.x = (int)(node - row * (uint32_t)I.nx);
+  c.y = (int)(row - z * (uint32_t)I.ny);
+  c.z = (int)z;
+  return c;
+}
+
+__device__ __forceinline__ uint32_t node_index(const InstDev& I, int x, int y, int z) {
+  return (uint32_t)x + (uint32_t)I.nx * ((uint32_t)y + (uint32_t)I.ny * (uint32_t)z);
+}
+
+// Resolves the lattice site (x,y,z) + off for neighbour lookups: periodic
+// faces wrap, any other face leaves the domain (returns false).
+__device__ __forceinline__ bool resolve_nb(const InstDev& I, int x, int y, int z, int ox, int oy,
+                                           int oz, uint32_t& out) {
+  int s[3] = {x + ox, y + oy, z + oz};
+  const int n[3] = {I.nx, I.ny, I.nz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (s[a] >= 0 && s[a] < n[a]) continue;
+    if (I.face[2 * a + (s[a] < 0 ? 0 : 1)] != LBM_FACE_PERIODIC) return false;
+    s[a] = (s[a] % n[a] + n[a]) % n[a];
+  }
+  out = node_index(I, s[0], s[1], s[2]);
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Prescribed-motion bodies (FP64).  Time t is the step count.
+// ---------------------------------------------------------------------------
+__device__ bool body_inside(const InstDev& I, double x, double y, double z, double t) {
+  const double* p = I.body;
+  switch (I.body_kind) {
+    case LBM_BODY_SPHERE: {
+      const double s = sin(p[7] * t + p[8]);
+      const double dx = x - (p[0] + p[4] * s);
+      const double dy = y - (p[1] + p[5] * s);
+      double r2 = dx * dx + dy * dy;
+      if (I.D == 3) {
+        const double dz = z - (p[2] + p[6] * s);
+        r2 += dz * dz;
+      }
+      return r2 <= p[3] * p[3];
+    }
+    case LBM_BODY_FLAP: {
+      const double sl = y - p[6];
+      if (sl < 0.0 || sl > p[1]) return false;
+      const double xc = p[0] + p[3] * sin(p[4] * t + p[5]) * (sl / p[1]) * (sl / p[1]);
+      return fabs(x - xc) <= 0.5 * p[2];
+    }
+    case LBM_BODY_PLATES:
+      return y < p[0] || y > p[1];
+    default:
+      return false;
+  }
+}
+
+__device__ void body_velocity(const InstDev& I, double x, double y, double z, double t,
+                              double (&v)[3]) {
+  const double* p = I.body;
+  v[0] = v[1] = v[2] = 0.0;
+  switch (I.body_kind) {
+    case LBM_BODY_SPHERE: {
+      const double c = cos(p[7] * t + p[8]);
+      for (int a = 0; a < I.D; ++a) v[a] = p[4 + a] * p[7] * c;
+      break;
+    }
+    case LBM_BODY_FLAP: {
+      double sl = y - p[6];
+      sl = fmin(fmax(sl, 0.0), p[1]);
+      v[0] = p[3] * p[4] * cos(p[4] * t + p[5]) * (sl / p[1]) * (sl / p[1]);
+      break;
+    }
+    case LBM_BODY_PLATES: {
+      const double* u = (y < 0.5 * (p[0] + p[1])) ? &p[2] : &p[5];
+      for (int a = 0; a < I.D; ++a) v[a] = u[a];
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// Wall fraction q in (0,1] of the link from fluid node x towards x - c, whose
+// far end is inside the body, and the body velocity at the wall point.
+// Sphere: smaller root of |x - lambda c - X_c|^2 = R^2; other bodies:
+// bisection to the first inside point.
+__device__ void body_cut(const InstDev& I, int x, int y, int z, int c0, int c1, int c2, double t,
+                         double& q, double (&uw)[3]) {
+  if (I.body_kind == LBM_BODY_SPHERE) {
+    const double* p = I.body;
+    const double s = sin(p[7] * t + p[8]);
+    const double d0 = x - (p[0] + p[4] * s), d1 = y - (p[1] + p[5] * s);
+    const double d2 = (I.D == 3) ? z - (p[2] + p[6] * s) : 0.0;
+    const double cc = (double)(c0 * c0 + c1 * c1 + c2 * c2);
+    const double dc = d0 * c0 + d1 * c1 + d2 * c2;
+    const double dd = d0 * d0 + d1 * d1 + d2 * d2 - p[3] * p[3];
+    const double disc = fmax(dc * dc - cc * dd, 0.0);
+    q = (dc - sqrt(disc)) / cc;
+    q = fmin(fmax(q, 0.0), 1.0);
+  } else {
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 60; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (body_inside(I, x - mid * c0, y - mid * c1, z - mid * c2, t)) hi = mid; else lo = mid;
+    }
+    q = hi;
+  }
+  body_velocity(I, x - q * c0, y - q * c1, z - q * c2, t, uw);
+}
+
+__device__ void inflow_velocity(const InstDev& I, int y, int z, double t, double (&u)[3]) {
+  double prof = 1.0;
+  if (I.inlet_profile == 1) {
+    const double yp = y + 0.5, H = I.ny;
+    prof = 1.5 * yp * (H - yp) / (0.25 * H * H);
+    if (I.D == 3) {
+      const double zp = z + 0.5, Z = I.nz;
+      prof *= 1.5 * zp * (Z - zp) / (0.25 * Z * Z);
+    }
+  }
+  double r = 1.0;
+  if (I.ramp_steps > 0) {
+    const double tt = fmin(t, (double)I.ramp_steps);
+    r = 0.5 * (1.0 - cos(M_PI * tt / I.ramp_steps));
+  }
+  for (int a = 0; a < 3; ++a) u[a] = I.u_in[a] * prof * r;
+}
+
+// ---------------------------------------------------------------------------
+// Lagged moments (post-collision state stored at the node itself).
+// ---------------------------------------------------------------------------
+template <int Q, int ST>
+__device__ __forceinline__ void lagged(const typename Store<ST>::T* sb, int64_t stride, uint32_t m,
+                                       typename Store<ST>::R& rt,
+                                       typename Store<ST>::R (&u)[3]) {
+  using R = typename Store<ST>::R;
+  R d[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) d[i] = Store<ST>::dec(sb[i * stride + m]);
+  R j[3];
+  moments_dev<Q>(d, rt, j);
+  const R ir = R(1) / (R(1) + rt);
+  for (int a = 0; a < 3; ++a) u[a] = j[a] * ir;
+}
+
+// ---------------------------------------------------------------------------
+// Pre-collision state of one node (any node: bulk, face or cut links):
+// pull streaming f_i(x) = A_i(x - c_i) (Eq. 1), missing populations from
+// Grad's approximation (Sec. II.C.1), inflow / outflow equilibria.
+//   sb   : instance base of the state being streamed (post-collision at t-1)
+//   t1   : time of the new state (geometry and inflow ramp)
+// Returns the deviations f_i - W_i.
+// ---------------------------------------------------------------------------
+template <int Q, int ST>
+__device__ void gather_pre(const InstDev& I, const typename Store<ST>::T* sb, const uint8_t* fl,
+                           int x, int y, int z, double t1, typename Store<ST>::R (&f)[Q]) {
+  using S = Store<ST>;
+  using R = typename S::R;
+  constexpr int D = dims<Q>();
+  const int64_t stride = I.stride;
+  const int n[3] = {I.nx, I.ny, I.nz};
+  uint32_t miss = 0, wallm = 0;
+  bool inlet = false, outlet = false;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int s[3] = {x - cx(i), y - cy(i), z - cz<Q>(i)};
+    bool w = false, in = false, out = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (s[a] >= 0 && s[a] < n[a]) continue;
+      const int fc = I.face[2 * a + (s[a] < 0 ? 0 : 1)];
+      if (fc == LBM_FACE_PERIODIC) s[a] = (s[a] + n[a]) % n[a];
+      else if (fc == LBM_FACE_WALL) w = true;
+      else if (fc == LBM_FACE_INLET) in = true;
+      else out = true;
+    }
+    f[i] = R(0);
+    if (w) {
+      miss |= 1u << i;
+      wallm |= 1u << i;
+    } else if (in) {
+      inlet = true;
+    } else if (out) {
+      outlet = true;
+    } else {
+      const uint32_t m = node_index(I, s[0], s[1], s[2]);
+      if (fl && (fl[m] & FLAG_SOLID)) miss |= 1u << i;
+      else f[i] = S::dec(sb[i * stride + m]);
+    }
+  }
+  if (inlet) {
+    // Equilibrium at the inflow velocity and the lagged density of x + e_x.
+    double ud[3];
+    inflow_velocity(I, y, z, t1, ud);
+    R rt = R(0), uu[3];
+    uint32_t m;
+    if (resolve_nb(I, x, y, z, 1, 0, 0, m) && !(fl && (fl[m] & FLAG_SOLID))) lagged<Q, ST>(sb, stride, m, rt, uu);
+    const R ui[3] = {(R)ud[0], (R)ud[1], (R)ud[2]};
+    feq_dev<Q, R>(rt, ui, f);
+    return;
+  }
+  if (outlet) {
+    // Equilibrium at density 1 and the lagged velocity of x - e_x.
+    R rt = R(0), uo[3] = {R(0), R(0), R(0)};
+    uint32_t m;
+    if (resolve_nb(I, x, y, z, -1, 0, 0, m) && !(fl && (fl[m] & FLAG_SOLID))) lagged<Q, ST>(sb, stride, m, rt, uo);
+    feq_dev<Q, R>(R(0), uo, f);
+    return;
+  }
+  if (!miss) return;
+
+  // ---- Grad's approximation for the missing populations ----------------
+  const double tq = t1;
+  auto link = [&](int i, R& q, R (&uw)[3]) {
+    if ((wallm >> i) & 1u) {
+      q = R(0.5);
+      uw[0] = uw[1] = uw[2] = R(0);
+    } else {
+      double qd, ud[3];
+      body_cut(I, x, y, z, cx(i), cy(i), cz<Q>(i), tq, qd, ud);
+      q = (R)qd;
+      for (int a = 0; a < 3; ++a) uw[a] = (R)ud[a];
+    }
+  };
+  auto fluid_at = [&](int ox, int oy, int oz, uint32_t& m) -> bool {
+    if (!resolve_nb(I, x, y, z, ox, oy, oz, m)) return false;
+    return !(fl && (fl[m] & FLAG_SOLID));
+  };
+  const uint32_t me = node_index(I, x, y, z);
+  R rt_x, u_x[3];
+  lagged<Q, ST>(sb, stride, me, rt_x, u_x);
+  const R rho_n = R(1) + rt_x;
+
+  // Target density: bounce-back-implied density plus the wall-motion term.
+  R rtt = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (!((miss >> i) & 1u)) {
+      rtt += f[i];
+    } else {
+      R q, uw[3];
+      link(i, q, uw);
+      const R cu = R(cx(i)) * uw[0] + R(cy(i)) * uw[1] + R(cz<Q>(i)) * uw[2];
+      rtt += S::dec(sb[(Q - 1 - i) * stride + me]) + R(6.0 * weight<Q>(i)) * rho_n * cu;
+    }
+  }
+  const R rho_t = R(1) + rtt;
+
+  // Target velocity: interpolation along each missing link through the wall
+  // point (s = -q) and the lagged velocities at x + c_i (s = 1), x + 2 c_i
+  // (s = 2), averaged over the missing links.
+  R ut[3] = {R(0), R(0), R(0)};
+  int nm = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (!((miss >> i) & 1u)) continue;
+    R q, uw[3];
+    link(i, q, uw);
+    uint32_t m1, m2;
+    R ui[3];
+    if (fluid_at(cx(i), cy(i), cz<Q>(i), m1)) {
+      R r1, u1[3];
+      lagged<Q, ST>(sb, stride, m1, r1, u1);
+      if (fluid_at(2 * cx(i), 2 * cy(i), 2 * cz<Q>(i), m2)) {
+        R r2, u2[3];
+        lagged<Q, ST>(sb, stride, m2, r2, u2);
+        const R a0 = R(2) / ((R(1) + q) * (R(2) + q));
+        const R a1 = R(2) * q / (R(1) + q);
+        const R a2 = -q / (R(2) + q);
+        for (int a = 0; a < 3; ++a) ui[a] = a0 * uw[a] + a1 * u1[a] + a2 * u2[a];
+      } else {
+        for (int a = 0; a < 3; ++a) ui[a] = (uw[a] + q * u1[a]) / (R(1) + q);
+      }
+    } else {
+      for (int a = 0; a < 3; ++a) ui[a] = uw[a];
+    }
+    for (int a = 0; a < 3; ++a) ut[a] += ui[a];
+    ++nm;
+  }
+  for (int a = 0; a < 3; ++a) ut[a] /= R(nm);
+
+  // Velocity gradient G[a][b] = d u_a / d x_b: central differences of the
+  // lagged velocity, the wall point on a cut side (quadratic through the wall
+  // point, x + e, x + 2e; linear if x + 2e is not fluid).
+  R G[3][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}, {R(0), R(0), R(0)}};
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    const int ip = axis_pop<Q>(b, +1);   // link to x - e_b
+    const int im = axis_pop<Q>(b, -1);   // link to x + e_b
+    const bool cut_m = (miss >> ip) & 1u;
+    const bool cut_p = (miss >> im) & 1u;
+    const int eb[3] = {b == 0, b == 1, b == 2};
+    uint32_t p1, p2, m1, m2;
+    R up1[3], up2[3], um1[3], um2[3], rr;
+    const bool fp1 = fluid_at(eb[0], eb[1], eb[2], p1);
+    const bool fp2 = fp1 && fluid_at(2 * eb[0], 2 * eb[1], 2 * eb[2], p2);
+    const bool fm1 = fluid_at(-eb[0], -eb[1], -eb[2], m1);
+    const bool fm2 = fm1 && fluid_at(-2 * eb[0], -2 * eb[1], -2 * eb[2], m2);
+    if (fp1) lagged<Q, ST>(sb, stride, p1, rr, up1);
+    if (fp2) lagged<Q, ST>(sb, stride, p2, rr, up2);
+    if (fm1) lagged<Q, ST>(sb, stride, m1, rr, um1);
+    if (fm2) lagged<Q, ST>(sb, stride, m2, rr, um2);
+    R qm = R(0), qp = R(0), wm[3] = {R(0), R(0), R(0)}, wp[3] = {R(0), R(0), R(0)};
+    if (cut_m) link(ip, qm, wm);
+    if (cut_p) link(im, qp, wp);
+    for (int a = 0; a < D; ++a) {
+      R g = R(0);
+      if (cut_m && cut_p) {
+        g = (wp[a] - wm[a]) / (qp + qm);
+      } else if (cut_m) {
+        if (fp2)
+          g = R(-3) * wm[a] / ((R(1) + qm) * (R(2) + qm)) + up1[a] * (R(2) - qm) / (R(1) + qm) +
+              up2[a] * (qm - R(1)) / (R(2) + qm);
+        else if (fp1)
+          g = (up1[a] - wm[a]) / (R(1) + qm);
+      } else if (cut_p) {
+        if (fm2)
+          g = R(3) * wp[a] / ((R(1) + qp) * (R(2) + qp)) - um1[a] * (R(2) - qp) / (R(1) + qp) -
+              um2[a] * (qp - R(1)) / (R(2) + qp);
+        else if (fm1)
+          g = (wp[a] - um1[a]) / (R(1) + qp);
+      } else if (fp1 && fm1) {
+        g = R(0.5) * (up1[a] - um1[a]);
+      } else if (fp1) {
+        g = up1[a] - u_x[a];
+      } else if (fm1) {
+        g = u_x[a] - um1[a];
+      }
+      G[a][b] = g;
+    }
+  }
+  // Pi = rho/3 I + rho u u - rho/(6 beta) (G + G^T)   (Pi^eq + Pi^neq, cs^2 = 1/3)
+  const R kneq = rho_t / (R(6) * (R)I.beta);
+  R Pi[6];
+  Pi[0] = rho_t / R(3) + rho_t * ut[0] * ut[0] - kneq * R(2) * G[0][0];
+  Pi[1] = rho_t / R(3) + rho_t * ut[1] * ut[1] - kneq * R(2) * G[1][1];
+  Pi[2] = rho_t / R(3) + rho_t * ut[2] * ut[2] - kneq * R(2) * G[2][2];
+  Pi[3] = rho_t * ut[0] * ut[1] - kneq * (G[0][1] + G[1][0]);
+  Pi[4] = rho_t * ut[0] * ut[2] - kneq * (G[0][2] + G[2][0]);
+  Pi[5] = rho_t * ut[1] * ut[2] - kneq * (G[1][2] + G[2][1]);
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    if ((miss >> i) & 1u) f[i] = grad_dev<Q, R>(i, rho_t, ut, Pi);
+}
+
+// ---------------------------------------------------------------------------
+// Statistics reduction within a workgroup (wave64 shuffles + LDS).
+// ---------------------------------------------------------------------------
+template <int BLOCK>
+__device__ void block_stats(float gmin, float gmax, double gsum, uint32_t cnt, uint32_t f64,
+                            StatPartial* out) {
+  for (int off = 32; off > 0; off >>= 1) {
+    gmin = fminf(gmin, __shfl_xor(gmin, off));
+    gmax = fmaxf(gmax, __shfl_xor(gmax, off));
+    gsum += __shfl_xor(gsum, off);
+    cnt += __shfl_xor(cnt, off);
+    f64 += __shfl_xor(f64, off);
+  }
+  constexpr int NW = BLOCK / 64;
+  __shared__ StatPartial sh[NW > 0 ? NW : 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = StatPartial{gmin, gmax, gsum, cnt, f64};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    StatPartial r = sh[0];
+    for (int k = 1; k < NW; ++k) {
+      r.gmin = fminf(r.gmin, sh[k].gmin);
+      r.gmax = fmaxf(r.gmax, sh[k].gmax);
+      r.gsum += sh[k].gsum;
+      r.count += sh[k].count;
+      r.fp64 += sh[k].fp64;
+    }
+    *out = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Bulk kernel: fused pull-stream + collide, one thread per node.
+// ---------------------------------------------------------------------------
+template <int Q, int ST, int BLOCK, int WAVES, bool STATS>
+__global__ void __launch_bounds__(BLOCK, WAVES)
+    k_bulk(StepBuffers b, const Tile* __restrict__ tiles, int tile0) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  using R = typename S::R;
+  const int ti = tile0 + blockIdx.x;
+  const Tile tl = tiles[ti];
+  const InstDev& I = b.insts[tl.inst];
+  const int nx = I.nx, ny = I.ny;
+  const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+  const int64_t stride = I.stride;
+  const T* __restrict__ sb = static_cast<const T*>(b.src) + I.pop_off;
+  T* __restrict__ db = static_cast<T*>(b.dst) + I.pop_off;
+  const uint8_t* fl = I.flag_off >= 0 ? b.flags + I.flag_off : nullptr;
+  CollideParams<R> P;
+  P.beta = (R)I.beta;
+  P.inv_beta = (R)(1.0 / I.beta);
+  P.beta_d = I.beta;
+  P.lbgk = I.collision;
+  P.trace_in_s = I.trace_in_s;
+  float gmin = 1e30f, gmax = -1e30f;
+  double gsum = 0.0;
+  uint32_t cnt = 0, f64 = 0;
+  for (int k = threadIdx.x; k < tl.count; k += BLOCK) {
+    const uint32_t node = (uint32_t)(tl.node0 + k);
+    if (fl && (fl[node] & FLAG_SPECIAL)) continue;
+    const Coord c = node_coord(I, node);
+    const uint32_t xm = c.x == 0 ? nx - 1 : c.x - 1;
+    const uint32_t xp = c.x == nx - 1 ? 0 : c.x + 1;
+    const uint32_t y0 = (uint32_t)c.y * nx;
+    const uint32_t ym = (uint32_t)(c.y == 0 ? ny - 1 : c.y - 1) * nx;
+    const uint32_t yp = (uint32_t)(c.y == ny - 1 ? 0 : c.y + 1) * nx;
+    uint32_t z0 = 0, zm = 0, zp = 0;
+    if (Q == 27) {
+      const int nz = I.nz;
+      z0 = (uint32_t)c.z * plane;
+      zm = (uint32_t)(c.z == 0 ? nz - 1 : c.z - 1) * plane;
+      zp = (uint32_t)(c.z == nz - 1 ? 0 : c.z + 1) * plane;
+    }
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const uint32_t sx = cx(i) == 0 ? (uint32_t)c.x : (cx(i) > 0 ? xm : xp);
+      const uint32_t sy = cy(i) == 0 ? y0 : (cy(i) > 0 ? ym : yp);
+      const uint32_t sz = cz<Q>(i) == 0 ? z0 : (cz<Q>(i) > 0 ? zm : zp);
+      f[i] = S::dec(sb[i * stride + (sx + sy + sz)]);
+    }
+    CollideOut co;
+    if (!collide<Q, R>(f, P, co)) atomicOr(b.err, 1u);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) db[i * stride + node] = S::enc(f[i]);
+    if (STATS) {
+      gmin = fminf(gmin, co.gamma);
+      gmax = fmaxf(gmax, co.gamma);
+      gsum += co.gamma;
+      cnt += 1;
+      f64 += co.fp64;
+    }
+  }
+  if (STATS) block_stats<BLOCK>(gmin, gmax, gsum, cnt, f64, b.stats + ti);
+}
+
+// ---------------------------------------------------------------------------
+// Boundary kernel: special nodes of the scanned regions.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool box_local(const Region& rg, int64_t local, int& x, int& y, int& z) {
+  const int64_t ex = rg.hi[0] - rg.lo[0], ey = rg.hi[1] - rg.lo[1];
+  x = rg.lo[0] + (int)(local % ex);
+  const int64_t r = local / ex;
+  y = rg.lo[1] + (int)(r % ey);
+  z = rg.lo[2] + (int)(r / ey);
+  return z < rg.hi[2];
+}
+
+__device__ __forceinline__ bool in_region(const Region& rg, int x, int y, int z) {
+  return x >= rg.lo[0] && x < rg.hi[0] && y >= rg.lo[1] && y < rg.hi[1] && z >= rg.lo[2] &&
+         z < rg.hi[2];
+}
+
+template <int Q, int ST>
+__global__ void __launch_bounds__(256) k_boundary(StepBuffers b, const Region* __restrict__ regions,
+                                                  const BoxTile* __restrict__ btiles, int bt0,
+                                                  int stat0) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  using R = typename S::R;
+  const BoxTile bt = btiles[bt0 + blockIdx.x];
+  const Region rg = regions[bt.region];
+  const InstDev& I = b.insts[rg.inst];
+  const T* sb = static_cast<const T*>(b.src) + I.pop_off;
+  T* db = static_cast<T*>(b.dst) + I.pop_off;
+  const uint8_t* fl = I.flag_off >= 0 ? b.flags + I.flag_off : nullptr;
+  const double t1 = (double)(*b.clock + 1);
+  CollideParams<R> P;
+  P.beta = (R)I.beta;
+  P.inv_beta = (R)(1.0 / I.beta);
+  P.beta_d = I.beta;
+  P.lbgk = I.collision;
+  P.trace_in_s = I.trace_in_s;
+  float gmin = 1e30f, gmax = -1e30f;
+  double gsum = 0.0;
+  uint32_t cnt = 0, f64 = 0;
+  for (int k = threadIdx.x; k < bt.count; k += 256) {
+    int x, y, z;
+    if (!box_local(rg, bt.local0 + k, x, y, z)) continue;
+    bool owned = true;
+    for (int r = rg.first; r < bt.region; ++r)
+      if (in_region(regions[r], x, y, z)) owned = false;
+    if (!owned) continue;
+    const uint32_t node = node_index(I, x, y, z);
+    if (!fl) continue;
+    const uint8_t fv = fl[node];
+    if ((fv & FLAG_SOLID) || !(fv & (FLAG_STATIC | FLAG_BODY))) continue;
+    R f[Q];
+    gather_pre<Q, ST>(I, sb, fl, x, y, z, t1, f);
+    CollideOut co;
+    if (!collide<Q, R>(f, P, co)) atomicOr(b.err, 1u);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) db[i * I.stride + node] = S::enc(f[i]);
+    gmin = fminf(gmin, co.gamma);
+    gmax = fmaxf(gmax, co.gamma);
+    gsum += co.gamma;
+    cnt += 1;
+    f64 += co.fp64;
+  }
+  if (b.stats) block_stats<256>(gmin, gmax, gsum, cnt, f64, b.stats + stat0 + blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Geometry kernels over the swept boxes of moving bodies.
+// ---------------------------------------------------------------------------
+template <int Q, int ST>
+__global__ void __launch_bounds__(256) k_geometry(int stage, const InstDev* __restrict__ insts,
+                                                  const Region* __restrict__ regions,
+                                                  const BoxTile* __restrict__ gtiles, void* src,
+                                                  uint8_t* flags, const int64_t* clock, int toff) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  using R = typename S::R;
+  const BoxTile gt = gtiles[blockIdx.x];
+  const Region rg = regions[gt.region];
+  const InstDev& I = insts[rg.inst];
+  uint8_t* fl = flags + I.flag_off;
+  const double t = (double)(*clock + toff);
+  const int k = threadIdx.x;
+  if (k >= gt.count) return;
+  int x, y, z;
+  if (!box_local(rg, gt.local0 + k, x, y, z)) return;
+  const uint32_t node = node_index(I, x, y, z);
+  const uint8_t fv = fl[node];
+  if (stage == 0) {
+    const bool in = body_inside(I, x, y, z, t);
+    fl[node] = (uint8_t)((fv & ~FLAG_SOLID_NEXT) | (in ? FLAG_SOLID_NEXT : 0));
+  } else if (stage == 1) {
+    // Fresh node (solid now, fluid at the next time): equilibrium at the mean
+    // lagged density of neighbours that are fluid now and the body velocity.
+    if (!((fv & FLAG_SOLID) && !(fv & FLAG_SOLID_NEXT))) return;
+    T* sb = static_cast<T*>(src) + I.pop_off;
+    R sum = R(0);
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (i == rest<Q>()) continue;
+      uint32_t m;
+      if (!resolve_nb(I, x, y, z, cx(i), cy(i), cz<Q>(i), m)) continue;
+      if (fl[m] & FLAG_SOLID) continue;
+      R rt, uu[3];
+      lagged<Q, ST>(sb, I.stride, m, rt, uu);
+      sum += R(1) + rt;
+      ++cnt;
+    }
+    const R rb = cnt ? sum / R(cnt) : R(1);
+    double ub[3];
+    body_velocity(I, x, y, z, t, ub);
+    const R u[3] = {(R)ub[0], (R)ub[1], (R)ub[2]};
+    R fe[Q];
+    feq_dev<Q, R>(rb - R(1), u, fe);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) sb[i * I.stride + node] = S::enc(fe[i]);
+  } else {
+    // SOLID_NEXT becomes current; fluid nodes with a solid x - c_i are cut.
+    const bool solid = fv & FLAG_SOLID_NEXT;
+    bool cut = false;
+    if (!solid) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        uint32_t m;
+        if (resolve_nb(I, x, y, z, -cx(i), -cy(i), -cz<Q>(i), m) && (fl[m] & FLAG_SOLID_NEXT))
+          cut = true;
+      }
+    }
+    fl[node] = (uint8_t)((fv & (FLAG_STATIC | FLAG_SOLID_NEXT)) | (solid ? FLAG_SOLID : 0) |
+                         (cut ? FLAG_BODY : 0));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation, checkpoint encode/decode, moments.
+// ---------------------------------------------------------------------------
+template <int Q, int ST>
+__global__ void k_init_eq(const InstDev* __restrict__ insts, int inst, int64_t N,
+                          const double* __restrict__ rho, const double* __restrict__ u, void* buf) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const InstDev& I = insts[inst];
+  const double uu[3] = {u[n], u[N + n], dims<Q>() == 3 ? u[2 * N + n] : 0.0};
+  double fe[Q];
+  feq_dev<Q, double>(rho[n] - 1.0, uu, fe);
+  T* db = static_cast<T*>(buf) + I.pop_off;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) db[i * I.stride + n] = S::enc_d(fe[i]);
+}
+
+template <int Q, int ST>
+__global__ void k_decode(const InstDev* __restrict__ insts, int inst, int64_t N, const void* buf,
+                         double* __restrict__ f) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const InstDev& I = insts[inst];
+  const T* sb = static_cast<const T*>(buf) + I.pop_off;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) f[i * N + n] = weight<Q>(i) + (double)S::dec(sb[i * I.stride + n]);
+}
+
+template <int Q, int ST>
+__global__ void k_encode(const InstDev* __restrict__ insts, int inst, int64_t N,
+                         const double* __restrict__ f, void* buf) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const InstDev& I = insts[inst];
+  T* db = static_cast<T*>(buf) + I.pop_off;
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    db[i * I.stride + n] = S::enc_d(f[i * N + n] - weight<Q>(i));
+}
+
+template <int BLOCK, int W>
+__device__ void block_sum_doubles(double (&v)[W], double* out) {
+  for (int off = 32; off > 0; off >>= 1)
+    for (int k = 0; k < W; ++k) v[k] += __shfl_xor(v[k], off);
+  constexpr int NW = BLOCK / 64;
+  __shared__ double sh[NW][W];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int k = 0; k < W; ++k) sh[w][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < W; ++k) {
+      double s = 0.0;
+      for (int j = 0; j < NW; ++j) s += sh[j][k];
+      out[k] = s;
+    }
+}
+
+template <int Q, int ST>
+__global__ void __launch_bounds__(256) k_moments(const InstDev* __restrict__ insts, int inst,
+                                                 int64_t N, const void* buf,
+                                                 const uint8_t* flags, double* rho, double* u,
+                                                 double* partials) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const InstDev& I = insts[inst];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (n < N) {
+    const T* sb = static_cast<const T*>(buf) + I.pop_off;
+    const bool solid = I.flag_off >= 0 && (flags[I.flag_off + n] & FLAG_SOLID);
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    if (!solid) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const double d = (double)S::dec(sb[i * I.stride + n]);
+        r += d;
+        j[0] += cx(i) * d;
+        j[1] += cy(i) * d;
+        j[2] += cz<Q>(i) * d;
+      }
+      r += 1.0;
+    }
+    const double ir = solid ? 0.0 : 1.0 / r;
+    if (rho) rho[n] = r;
+    if (u)
+      for (int a = 0; a < dims<Q>(); ++a) u[a * N + n] = j[a] * ir;
+    acc[0] = r;
+    acc[1] = j[0];
+    acc[2] = j[1];
+    acc[3] = j[2];
+  }
+  block_sum_doubles<256, 4>(acc, partials + 4 * blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Wall force (Sec. II.C.2).
+// ---------------------------------------------------------------------------
+template <int Q, int ST>
+__device__ void node_stress(const InstDev& I, const typename Store<ST>::T* sb, const uint8_t* fl,
+                            uint32_t m, double t, double (&sig)[6]) {
+  using R = typename Store<ST>::R;
+  const Coord c = node_coord(I, m);
+  R f[Q];
+  gather_pre<Q, ST>(I, sb, fl, c.x, c.y, c.z, t, f);
+  R rt, j[3];
+  moments_dev<Q>(f, rt, j);
+  const R rho = R(1) + rt;
+  const R u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+  R fe[Q];
+  feq_dev<Q, R>(rt, u, fe);
+  R P[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R dl = f[i] - fe[i];
+    P[0] += R(cx(i) * cx(i)) * dl;
+    P[1] += R(cy(i) * cy(i)) * dl;
+    P[2] += R(cz<Q>(i) * cz<Q>(i)) * dl;
+    P[3] += R(cx(i) * cy(i)) * dl;
+    P[4] += R(cx(i) * cz<Q>(i)) * dl;
+    P[5] += R(cy(i) * cz<Q>(i)) * dl;
+  }
+  const double k = 1.0 - I.beta, p = (double)rho / 3.0;
+  for (int e = 0; e < 6; ++e) sig[e] = -k * (double)P[e] - (e < 3 ? p : 0.0);
+  if (dims<Q>() == 2) sig[2] = sig[4] = sig[5] = 0.0;
+}
+
+// Stress at an off-lattice point: (bi/tri)linear over the surrounding fluid
+// nodes with renormalised weights, else the nearest fluid node in the 5^D box
+// around floor(p) (first in z, y, x order on ties).
+template <int Q, int ST>
+__device__ bool point_stress(const InstDev& I, const typename Store<ST>::T* sb, const uint8_t* fl,
+                             const double (&p)[3], double t, double (&sig)[6]) {
+  constexpr int D = dims<Q>();
+  int base[3] = {0, 0, 0};
+  double fr[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < D; ++a) {
+    base[a] = (int)floor(p[a]);
+    fr[a] = p[a] - base[a];
+  }
+  double acc[6] = {0, 0, 0, 0, 0, 0}, wsum = 0.0;
+  for (int k = 0; k < (1 << D); ++k) {
+    int off[3] = {0, 0, 0};
+    double w = 1.0;
+    for (int a = 0; a < D; ++a) {
+      off[a] = (k >> a) & 1;
+      w *= off[a] ? fr[a] : 1.0 - fr[a];
+    }
+    if (w <= 0.0) continue;
+    uint32_t m;
+    if (!resolve_nb(I, base[0], base[1], base[2], off[0], off[1], off[2], m)) continue;
+    if (fl && (fl[m] & FLAG_SOLID)) continue;
+    double s[6];
+    node_stress<Q, ST>(I, sb, fl, m, t, s);
+    for (int e = 0; e < 6; ++e) acc[e] += w * s[e];
+    wsum += w;
+  }
+  if (wsum > 0.0) {
+    for (int e = 0; e < 6; ++e) sig[e] = acc[e] / wsum;
+    return true;
+  }
+  double best = 1e300;
+  int64_t bestm = -1;
+  const int zr = D == 3 ? 2 : 0;
+  for (int dz = -zr; dz <= zr; ++dz)
+    for (int dy = -2; dy <= 2; ++dy)
+      for (int dx = -2; dx <= 2; ++dx) {
+        uint32_t m;
+        if (!resolve_nb(I, base[0], base[1], base[2], dx, dy, dz, m)) continue;
+        if (fl && (fl[m] & FLAG_SOLID)) continue;
+        const double q[3] = {(double)(base[0] + dx), (double)(base[1] + dy), (double)(base[2] + dz)};
+        double r2 = 0.0;
+        for (int a = 0; a < D; ++a) r2 += (q[a] - p[a]) * (q[a] - p[a]);
+        if (r2 < best) {
+          best = r2;
+          bestm = m;
+        }
+      }
+  if (bestm < 0) {
+    for (int e = 0; e < 6; ++e) sig[e] = 0.0;
+    return false;
+  }
+  node_stress<Q, ST>(I, sb, fl, (uint32_t)bestm, t, sig);
+  return true;
+}
+
+template <int Q, int ST>
+__global__ void __launch_bounds__(256) k_force(const InstDev* __restrict__ insts, int inst,
+                                               const void* prev, const uint8_t* flags,
+                                               const int64_t* clock, const double* xq,
+                                               const double* nq, const double* wq, int nqp,
+                                               double* traction, double* partials) {
+  constexpr int D = dims<Q>();
+  const InstDev& I = insts[inst];
+  const typename Store<ST>::T* sb = static_cast<const typename Store<ST>::T*>(prev) + I.pop_off;
+  const uint8_t* fl = I.flag_off >= 0 ? flags + I.flag_off : nullptr;
+  const double t = (double)(*clock);
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (q < nqp) {
+    double nv[3] = {0, 0, 0}, p1[3] = {0, 0, 0}, p2[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) {
+      nv[a] = nq[q * D + a];
+      p1[a] = xq[q * D + a] + nv[a];
+      p2[a] = xq[q * D + a] + 2.0 * nv[a];
+    }
+    double s1[6], s2[6];
+    const bool ok1 = point_stress<Q, ST>(I, sb, fl, p1, t, s1);
+    const bool ok2 = point_stress<Q, ST>(I, sb, fl, p2, t, s2);
+    double S[3][3];
+    const int ix[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) S[a][c] = 2.0 * s1[ix[a][c]] - s2[ix[a][c]];
+    for (int a = 0; a < D; ++a) {
+      double ta = 0.0;
+      for (int c = 0; c < D; ++c) ta += S[a][c] * nv[c];
+      if (traction) traction[q * D + a] = ta;
+      acc[a] = wq[q] * ta;
+    }
+    acc[3] = (ok1 && ok2) ? 0.0 : 1.0;
+  }
+  block_sum_doubles<256, 4>(acc, partials + 4 * blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Clock and reductions
+// ---------------------------------------------------------------------------
+__global__ void k_tick(int64_t* clock) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] += 1;
+}
+
+__global__ void __launch_bounds__(256) k_reduce(const double* partials, int n, int width,
+                                                double* out) {
+  // Fixed order: thread t sums partials t, t+256, ... sequentially, then a
+  // fixed tree over the threads.
+  __shared__ double sh[256];
+  for (int k = 0; k < width; ++k) {
+    double s = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) s += partials[(int64_t)j * width + k];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = sh[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_reduce_stats(const StatPartial* parts, int n, StatPartial* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  StatPartial r{1e30f, -1e30f, 0.0, 0u, 0u};
+  for (int j = 0; j < n; ++j) {
+    const StatPartial p = parts[j];
+    if (p.count == 0) continue;
+    r.gmin = fminf(r.gmin, p.gmin);
+    r.gmax = fmaxf(r.gmax, p.gmax);
+    r.gsum += p.gsum;
+    r.count += p.count;
+    r.fp64 += p.fp64;
+  }
+  *out = r;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers and variant table
+// ---------------------------------------------------------------------------
+struct BulkVariant {
+  const char* name;
+  int block, tile, waves;
+};
+
+static const BulkVariant kVariants[] = {
+    {"b256_t256_w1", 256, 256, 1},  {"b256_t512_w1", 256, 512, 1},
+    {"b128_t128_w1", 128, 128, 1},  {"b512_t512_w1", 512, 512, 1},
+    {"b256_t256_w2", 256, 256, 2},  {"b256_t1024_w2", 256, 1024, 2},
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+int bulk_variant_count() { return kNumVariants; }
+const char* bulk_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVariants[v].name : "?"; }
+int bulk_variant_tile(int v) { return kVariants[(v >= 0 && v < kNumVariants) ? v : 0].tile; }
+
+template <int Q, int ST, int BLOCK, int WAVES>
+static hipError_t launch_bulk_v(const StepBuffers& b, const Tile* tiles, int tile0, int ntiles,
+                                hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (b.stats)
+    hipLaunchKernelGGL((k_bulk<Q, ST, BLOCK, WAVES, true>), dim3(ntiles), dim3(BLOCK), 0, s, b,
+                       tiles, tile0);
+  else
+    hipLaunchKernelGGL((k_bulk<Q, ST, BLOCK, WAVES, false>), dim3(ntiles), dim3(BLOCK), 0, s, b,
+                       tiles, tile0);
+  return hipGetLastError();
+}
+
+template <int Q, int ST>
+static hipError_t launch_bulk(int v, const StepBuffers& b, const Tile* tiles, int tile0,
+                              int ntiles, hipStream_t s) {
+  switch (v) {
+    case 1: return launch_bulk_v<Q, ST, 256, 1>(b, tiles, tile0, ntiles, s);
+    case 2: return launch_bulk_v<Q, ST, 128, 1>(b, tiles, tile0, ntiles, s);
+    case 3: return launch_bulk_v<Q, ST, 512, 1>(b, tiles, tile0, ntiles, s);
+    case 4: return launch_bulk_v<Q, ST, 256, 2>(b, tiles, tile0, ntiles, s);
+    case 5: return launch_bulk_v<Q, ST, 256, 2>(b, tiles, tile0, ntiles, s);
+    default: return launch_bulk_v<Q, ST, 256, 1>(b, tiles, tile0, ntiles, s);
+  }
+}
+
+template <int Q, int ST>
+static hipError_t launch_boundary(const StepBuffers& b, const Region* regions,
+                                  const BoxTile* btiles, int bt0, int nbt, int stat0,
+                                  hipStream_t s) {
+  if (nbt <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_boundary<Q, ST>), dim3(nbt), dim3(256), 0, s, b, regions, btiles, bt0,
+                     stat0);
+  return hipGetLastError();
+}
+
+template <int Q, int ST>
+static hipError_t launch_geometry(int stage, const InstDev* insts, const Region* regions,
+                                  const BoxTile* gtiles, int ngt, void* src, uint8_t* flags,
+                                  const int64_t* clock, int toff, hipStream_t s) {
+  if (ngt <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_geometry<Q, ST>), dim3(ngt), dim3(256), 0, s, stage, insts, regions,
+                     gtiles, src, flags, clock, toff);
+  return hipGetLastError();
+}
+
+static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+template <int Q, int ST>
+static hipError_t launch_init(const InstDev* insts, int inst, int64_t N, const double* rho,
+                              const double* u, void* buf, hipStream_t s) {
+  hipLaunchKernelGGL((k_init_eq<Q, ST>), dim3(grid_for(N, 256)), dim3(256), 0, s, insts, inst, N,
+                     rho, u, buf);
+  return hipGetLastError();
+}
+
+template <int Q, int ST>
+static hipError_t launch_decode(const InstDev* insts, int inst, int64_t N, const void* buf,
+                                double* f, hipStream_t s) {
+  hipLaunchKernelGGL((k_decode<Q, ST>), dim3(grid_for(N, 256)), dim3(256), 0, s, insts, inst, N,
+                     buf, f);
+  return hipGetLastError();
+}
+
+template <int Q, int ST>
+static hipError_t launch_encode(const InstDev* insts, int inst, int64_t N, const double* f,
+                                void* buf, hipStream_t s) {
+  hipLaunchKernelGGL((k_encode<Q, ST>), dim3(grid_for(N, 256)), dim3(256), 0, s, insts, inst, N,
+                     f, buf);
+  return hipGetLastError();
+}
+
+template <int Q, int ST>
+static hipError_t launch_moments(const InstDev* insts, int inst, int64_t N, const void* buf,
+                                 const uint8_t* flags, double* rho, double* u, double* partials,
+                                 int* nparts, hipStream_t s) {
+  const unsigned g = grid_for(N, 256);
+  *nparts = (int)g;
+  hipLaunchKernelGGL((k_moments<Q, ST>), dim3(g), dim3(256), 0, s, insts, inst, N, buf, flags,
+                     rho, u, partials);
+  return hipGetLastError();
+}
+
+template <int Q, int ST>
+static hipError_t launch_force(const InstDev* insts, int inst, const void* prev,
+                               const uint8_t* flags, const int64_t* clock, const double* xq,
+                               const double* nq, const double* wq, int nqp, double* traction,
+                               double* partials, int* nparts, hipStream_t s) {
+  const unsigned g = grid_for(nqp, 256);
+  *nparts = (int)g;
+  if (g == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_force<Q, ST>), dim3(g), dim3(256), 0, s, insts, inst, prev, flags, clock,
+                     xq, nq, wq, nqp, traction, partials);
+  return hipGetLastError();
+}
+
+template <int Q, int ST>
+static const Ops* ops_for() {
+  static const Ops o = {launch_bulk<Q, ST>,     launch_boundary<Q, ST>, launch_geometry<Q, ST>,
+                        launch_init<Q, ST>,     launch_decode<Q, ST>,   launch_encode<Q, ST>,
+                        launch_moments<Q, ST>,  launch_force<Q, ST>};
+  return &o;
+}
+
+const Ops* get_ops(int Q, int storage) {
+  if (Q == 9) {
+    switch (storage) {
+      case LBM_F64: return ops_for<9, LBM_F64>();
+      case LBM_F32: return ops_for<9, LBM_F32>();
+      case LBM_F16_SHIFTED: return ops_for<9, LBM_F16_SHIFTED>();
+      case LBM_BF16_SHIFTED: return ops_for<9, LBM_BF16_SHIFTED>();
+    }
+  } else if (Q == 27) {
+    switch (storage) {
+      case LBM_F64: return ops_for<27, LBM_F64>();
+      case LBM_F32: return ops_for<27, LBM_F32>();
+      case LBM_F16_SHIFTED: return ops_for<27, LBM_F16_SHIFTED>();
+      case LBM_BF16_SHIFTED: return ops_for<27, LBM_BF16_SHIFTED>();
+    }
+  }
+  return nullptr;
+}
+
+hipError_t launch_tick(int64_t* clock, hipStream_t s) {
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, clock);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partials, int n, int width, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, n, width, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_stats(const StatPartial* parts, int n, StatPartial* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(64), 0, s, parts, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace kbc

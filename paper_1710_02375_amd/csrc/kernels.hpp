@@ -1,0 +1,83 @@
+// Launch interface between the host engine and the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_device.hpp"
+
+namespace kbc {
+
+// Per-workgroup gamma statistics of one step.
+struct StatPartial {
+  float gmin, gmax;
+  double gsum;
+  uint32_t count, fp64;
+};
+
+// A run of nodes of one scanned box (boundary and geometry kernels).
+struct BoxTile {
+  int region;     // index into the region table
+  int count;
+  int64_t local0; // first node index inside the box, x-fastest
+};
+
+struct StepBuffers {
+  const InstDev* insts;
+  const void* src;
+  void* dst;
+  const uint8_t* flags;   // flag pool (instance offsets in InstDev)
+  uint32_t* err;          // device error word
+  const int64_t* clock;   // steps taken before this step
+  StatPartial* stats;     // per-workgroup statistics, or null
+};
+
+struct Ops {
+  // Bulk stream-collide over tiles [tile0, tile0 + ntiles) for nodes with no
+  // special flag.  Statistics go to stats[tile index].
+  hipError_t (*bulk)(int variant, const StepBuffers& b, const Tile* tiles, int tile0, int ntiles,
+                     hipStream_t s);
+  // Special nodes (faces, cut links) of the scanned regions: streaming with
+  // Grad fill and face conditions, then collision.  Statistics go to
+  // stats[stat0 + box tile index].
+  hipError_t (*boundary)(const StepBuffers& b, const Region* regions, const BoxTile* btiles,
+                         int bt0, int nbt, int stat0, hipStream_t s);
+  // Geometry update over the swept boxes at time clock + toff:
+  // stage 0 marks SOLID_NEXT, stage 1 refills fresh nodes of src, stage 2
+  // makes SOLID_NEXT current and marks the cut-link (BODY) nodes.
+  hipError_t (*geometry)(int stage, const InstDev* insts, const Region* regions,
+                         const BoxTile* gtiles, int ngt, void* src, uint8_t* flags,
+                         const int64_t* clock, int toff, hipStream_t s);
+  // f := f^eq(rho, u) on every node of one instance (rho: N, u: D*N doubles).
+  hipError_t (*init_eq)(const InstDev* insts, int inst, int64_t N, const double* rho,
+                        const double* u, void* buf, hipStream_t s);
+  // Full populations (double, population-major) <-> storage.
+  hipError_t (*decode)(const InstDev* insts, int inst, int64_t N, const void* buf, double* f,
+                       hipStream_t s);
+  hipError_t (*encode)(const InstDev* insts, int inst, int64_t N, const double* f, void* buf,
+                       hipStream_t s);
+  // rho, u (nullable) and per-workgroup partial sums (mass, momentum) of one
+  // instance; returns the number of partials written through nparts.
+  hipError_t (*moments)(const InstDev* insts, int inst, int64_t N, const void* buf,
+                        const uint8_t* flags, double* rho, double* u, double* partials,
+                        int* nparts, hipStream_t s);
+  // Wall force (per point traction, per-workgroup partial force sums).
+  hipError_t (*force)(const InstDev* insts, int inst, const void* prev, const uint8_t* flags,
+                      const int64_t* clock, const double* xq, const double* nq,
+                      const double* wq, int nqp, double* traction, double* partials,
+                      int* nparts, hipStream_t s);
+};
+
+const Ops* get_ops(int Q, int storage);
+
+// Bulk-kernel variants (workgroup size, nodes per tile, waves per SIMD hint).
+int bulk_variant_count();
+const char* bulk_variant_name(int v);
+int bulk_variant_tile(int v);
+
+hipError_t launch_tick(int64_t* clock, hipStream_t s);
+// Sums `width` doubles over n partials in a fixed order into out[width].
+hipError_t launch_reduce(const double* partials, int n, int width, double* out, hipStream_t s);
+hipError_t launch_reduce_stats(const StatPartial* parts, int n, StatPartial* out, hipStream_t s);
+
+}  // namespace kbc

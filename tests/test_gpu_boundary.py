@@ -1,0 +1,221 @@
+"""GPU parity of the boundary path against the CPU oracle: Grad's
+approximation at cut links (Sec. II.C.1), face conditions, prescribed-motion
+bodies with fresh-node refill, the wall force (Sec. II.C.2), and batching of
+uneven instances in one launch.
+
+F64 runs share the oracle's arithmetic up to operation order, so populations
+agree to ~1e-13 after tens of steps; body geometry is evaluated in FP64 on both
+sides (device sin/cos vs host libm differ by an ulp, far below any decision
+margin in these cases)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def pair(Q, nx, ny, nz, nu, storage="f64", body=None, steps=0, rho=None, u=None, **kw):
+    from paper_1710_02375_amd import lbm
+
+    s = lbm.Solver([dict(Q=Q, nx=nx, ny=ny, nz=nz, nu=nu, storage=storage, **kw)])
+    okw = {k: v for k, v in kw.items() if k in ("faces", "u_in", "inlet_profile", "ramp_steps",
+                                                 "collision", "trace_in_s")}
+    if "collision" in okw:
+        okw["collision"] = 1 if okw["collision"] == "lbgk" else 0
+    d = oracle.Domain(Q, nx, ny, nz, nu, **okw)
+    N = nx * ny * nz
+    D = 3 if Q == 27 else 2
+    if rho is None:
+        rho, u = np.ones(N), np.zeros((D, N))
+    s.init_fields(rho, u)
+    d.init_fields(rho, u)
+    if body is not None:
+        s.set_body(*body)
+        d.set_body(*body)
+    return s, d
+
+
+def compare(s, d, tol, label):
+    fl = d.solid() == 0
+    fg, fo = s.get_populations(), d.get_populations()
+    err = np.max(np.abs(fg[:, fl] - fo[:, fl]))
+    _, ug, tg = s.moments()
+    _, uo, to = d.moments()
+    say("  %s: max |df| fluid = %.3e, mass gpu-oracle %.3e" % (label, err, tg["mass"] - to["mass"]))
+    assert err < tol, label
+    return ug, uo
+
+
+@pytest.mark.parametrize("qlo,qhi", [(0.25, 0.75), (0.5, 0.5)])
+def test_couette_plates_parity_and_shear(qlo, qhi):
+    ny, nx, U, nu = 14, 4, 0.02, 0.1
+    ylo, yhi = 1 - qlo, (ny - 2) + qhi
+    say("case: Couette plates q=%.2f/%.2f F64" % (qlo, qhi))
+    s, d = pair(9, nx, ny, 1, nu, body=(W.BODY_PLATES, W.plates_params(ylo, yhi, (0, 0, 0), (U, 0, 0))))
+    assert np.array_equal(s.moments()[0] == 0, d.solid() == 1)
+    for k in (1, 10, 400):
+        s.step(k)
+        d.step(k)
+    compare(s, d, 1e-13, "couette")
+    Fg, tg = s.wall_force(*W.plate_quadrature(ylo, 1.0, nx))
+    Fo, to, _ = d.wall_force(*W.plate_quadrature(ylo, 1.0, nx))
+    say("  force gpu %s oracle %s" % (Fg, Fo))
+    assert np.allclose(Fg, Fo, rtol=0, atol=1e-13)
+    assert np.allclose(tg, to, rtol=0, atol=1e-13)
+
+
+def test_channel_inlet_outlet_walls_parity():
+    nx, ny, ubar, nu = 40, 12, 0.03, 0.05
+    faces = ["inlet", "outlet", "wall", "wall", "periodic", "periodic"]
+    say("case: D2Q9 channel inlet/outlet/walls, ramp, F64")
+    s, d = pair(9, nx, ny, 1, nu, faces=faces, u_in=(ubar, 0, 0), inlet_profile=1, ramp_steps=50)
+    for k in (1, 5, 94, 300):
+        s.step(k)
+        d.step(k)
+        compare(s, d, 1e-12, "channel t=%d" % d.time)
+
+
+def test_channel_3d_walls_f64():
+    nx, ny, nz, nu = 16, 10, 8, 0.05
+    faces = ["inlet", "outlet", "wall", "wall", "periodic", "periodic"]
+    say("case: D3Q27 channel walls inlet/outlet F64")
+    s, d = pair(27, nx, ny, nz, nu, faces=faces, u_in=(0.03, 0, 0), inlet_profile=0, ramp_steps=20)
+    s.step(40)
+    d.step(40)
+    compare(s, d, 1e-12, "channel3d")
+
+
+def test_resting_sphere_fixed_point_and_zero_force():
+    n = 16
+    center = (7.3, 8.1, 7.7)
+    say("case: resting sphere F32")
+    s, d = pair(27, n, n, n, 0.05, storage="f32",
+                body=(W.BODY_SPHERE, W.sphere_params(center, 4.2)))
+    f0 = s.get_populations()
+    s.step(6)
+    f1 = s.get_populations()
+    solid = d.solid().astype(bool)
+    assert np.array_equal(f1[:, ~solid], f0[:, ~solid])
+    xq, nq, wq = W.sphere_quadrature(center, 4.2, subdiv=3)
+    F, tr = s.wall_force(xq, nq, wq)
+    say("  force %s" % F)
+    assert np.max(np.abs(F)) < 1e-5
+    assert np.allclose(tr, -nq / 3, atol=1e-6)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_moving_sphere_parity_with_fresh_nodes(storage, tol):
+    n = 24
+    center = (11.6, 12.2, 11.9)
+    amp, period = 3.0, 300.0
+    say("case: oscillating sphere %s n=%d" % (storage, n))
+    s, d = pair(27, n, n, n, 0.05, storage=storage,
+                body=(W.BODY_SPHERE, W.sphere_params(center, 4.0, (amp, 0.5, 0), period)))
+    for k in (1, 2, 20, 17):
+        s.step(k)
+        d.step(k)
+    ug, uo = compare(s, d, tol, "sphere %s t=%d" % (storage, d.time))
+    fl = d.solid() == 0
+    t = d.time
+    c = np.array(center) + np.array([amp, 0.5, 0]) * math.sin(2 * math.pi * t / period)
+    xq, nq, wq = W.sphere_quadrature(c, 4.0, subdiv=3)
+    Fg, tg = s.wall_force(xq, nq, wq)
+    Fo, to, st = d.wall_force(xq, nq, wq)
+    say("  force gpu %s oracle %s" % (Fg, Fo))
+    assert np.allclose(Fg, Fo, rtol=0, atol=50 * tol)
+    assert Fg[0] < 0
+
+
+def test_flap_channel_parity_f64():
+    ch = W.flap_channels(count=1, seed=2375)[0]
+    nx, ny = 96, 48
+    kind, p = ch["body"]
+    p = p.copy()
+    p[0] = 24.0
+    p[1] = 14.0
+    p[3] = 0.15 * 14.0
+    p[4] = 2 * math.pi / 200.0
+    say("case: flap channel F64 %dx%d" % (nx, ny))
+    s, d = pair(9, nx, ny, 1, ch["nu"], faces=ch["faces"], u_in=ch["u_in"], inlet_profile=1,
+                body=(kind, p))
+    for k in (1, 3, 46, 50):
+        s.step(k)
+        d.step(k)
+        compare(s, d, 1e-12, "flap t=%d" % d.time)
+
+
+def test_batched_equals_per_instance_and_oracle():
+    """Uneven flap channels in one context: the batched launch and one launch
+    per instance give bitwise equal states, and each matches its own oracle."""
+    from paper_1710_02375_amd import lbm
+
+    chans = W.flap_channels(count=5, seed=2375)
+    descs = []
+    for ch in chans:
+        nx, ny = min(ch["nx"], 160), min(ch["ny"], 64)
+        descs.append(dict(Q=9, nx=nx, ny=ny, nz=1, nu=ch["nu"], storage="f32", faces=ch["faces"],
+                          u_in=ch["u_in"], inlet_profile=1))
+    say("case: batched 5 channels F32, sizes %s" % [(d["nx"], d["ny"]) for d in descs])
+    outs = []
+    for mode in (0, 1):
+        s = lbm.Solver(descs)
+        s.set_launch_mode(mode)
+        for k, (ch, dsc) in enumerate(zip(chans, descs)):
+            N = dsc["nx"] * dsc["ny"]
+            s.init_fields(np.ones(N), np.zeros((2, N)), inst=k)
+            kind, p = ch["body"]
+            p = p.copy()
+            p[0] = dsc["nx"] / 4.0
+            p[1] = min(p[1], 0.35 * dsc["ny"])
+            p[3] = 0.15 * p[1]
+            p[4] = 2 * math.pi / 150.0
+            s.set_body(kind, p, inst=k)
+        s.step(40)
+        outs.append([s.get_populations(k) for k in range(len(descs))])
+        s.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    # instance 2 against its oracle
+    k = 2
+    ch, dsc = chans[k], descs[k]
+    d = oracle.Domain(9, dsc["nx"], dsc["ny"], 1, dsc["nu"], faces=dsc["faces"], u_in=dsc["u_in"],
+                      inlet_profile=1)
+    N = dsc["nx"] * dsc["ny"]
+    d.init_fields(np.ones(N), np.zeros((2, N)))
+    kind, p = ch["body"]
+    p = p.copy()
+    p[0] = dsc["nx"] / 4.0
+    p[1] = min(p[1], 0.35 * dsc["ny"])
+    p[3] = 0.15 * p[1]
+    p[4] = 2 * math.pi / 150.0
+    d.set_body(kind, p)
+    d.step(40)
+    fl = d.solid() == 0
+    w = oracle.lattice(9)[1][:, None]
+    err = np.max(np.abs(outs[0][k][:, fl] - d.get_populations()[:, fl]) / w)
+    say("  instance %d vs oracle: max |df|/W = %.3e" % (k, err))
+    assert err < 1e-5
+
+
+def test_geometry_errors():
+    from paper_1710_02375_amd import lbm
+
+    say("case: geometry errors")
+    s = lbm.Solver([dict(Q=27, nx=16, ny=16, nz=16, nu=0.05)])
+    with pytest.raises(lbm.LBMError) as ei:
+        s.set_body(W.BODY_SPHERE, W.sphere_params((8, 8, 8), 7.0, (3, 0, 0), 100.0))
+    assert ei.value.status == lbm.LBM_ERR_GEOMETRY
+    with pytest.raises(lbm.LBMError) as ei:
+        s.set_body(W.BODY_FLAP, W.flap_params(4, 4, 1, 1, 100))
+    assert ei.value.status == lbm.LBM_ERR_INVALID
+    with pytest.raises(lbm.LBMError) as ei:
+        s.wall_force(np.zeros((1, 3)), np.array([[1.0, 0, 0]]), np.ones(1))
+    assert ei.value.status == lbm.LBM_ERR_INVALID   # no step since set-up

@@ -1,0 +1,302 @@
+"""GPU parity of the periodic KBC step against the CPU oracle (through the C ABI).
+
+Tolerances:
+  F64 : same arithmetic up to operation order; after tens of steps the
+        populations agree to ~1e-14 absolute, velocity rel L2 <= 1e-12.
+  F32 : FP32 arithmetic (eps 6e-8) on equilibrium deviations up to 0.3 W_i,
+        about ten roundings deep with 1-ulp rcp/sqrt (~2e-7 W_i), passed to
+        the new state through the collision with gain beta*gamma <= 2.5: one
+        step agrees to |df_i| <= 1e-6 W_i; over many steps the velocity gate
+        is rel L2 <= 1e-5.
+  F16 / BF16 : the oracle rounds the shifted populations to the storage
+        format after every step (same rounding rule), so one step agrees to
+        one storage ulp, or to the FP32 arithmetic bound above where that is
+        larger (deviations near zero, whose BF16 ulp is tiny).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def solver(**kw):
+    from paper_1710_02375_amd import lbm
+
+    return lbm.Solver([kw])
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def oracle_run(Q, n, nu, rho, u, steps, **kw):
+    d = oracle.Domain(Q, n, n, n if Q == 27 else 1, nu, **kw)
+    d.init_fields(rho, u)
+    d.step(steps)
+    return d
+
+
+def lattice_w(Q):
+    return oracle.lattice(Q)[1]
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_bruteforce_f64_every_population(Q):
+    n, steps = 8, 50
+    say("case: brute force F64 Q=%d n=%d steps=%d" % (Q, n, steps))
+    if Q == 27:
+        rho, u, _ = W.taylor_green_3d(n, re=50.0, ma=0.15, perturb=0.05, seed=3)
+    else:
+        rho, u = W.taylor_green_2d(n, 0.05)
+        u = u + 0.002 * np.random.default_rng(3).uniform(-1, 1, size=u.shape)
+    nu = 0.02
+    s = solver(Q=Q, nx=n, ny=n, nz=n if Q == 27 else 1, nu=nu, storage="f64")
+    s.init_fields(rho, u)
+    d = oracle.Domain(Q, n, n, n if Q == 27 else 1, nu)
+    d.init_fields(rho, u)
+    worst = 0.0
+    for k in range(steps):
+        s.step(1)
+        d.step(1)
+        fg, fo = s.get_populations(), d.get_populations()
+        worst = max(worst, np.max(np.abs(fg - fo)))
+    say("  max |f_gpu - f_oracle| over all steps: %.3e" % worst)
+    assert worst < 1e-13
+    _, ug, tg = s.moments()
+    _, uo, to = d.moments()
+    assert np.linalg.norm(ug - uo) / np.linalg.norm(uo) < 1e-12
+    assert abs(tg["mass"] - to["mass"]) < 1e-11
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+@pytest.mark.parametrize("collision,trace_in_s", [("kbc", 1), ("lbgk", 0)])
+def test_variants_f64(Q, collision, trace_in_s):
+    n, steps = 8, 20
+    say("case: F64 Q=%d %s trace_in_s=%d" % (Q, collision, trace_in_s))
+    if Q == 27:
+        rho, u, _ = W.taylor_green_3d(n, re=50.0, ma=0.15, perturb=0.05, seed=4)
+    else:
+        rho, u = W.taylor_green_2d(n, 0.05)
+    s = solver(Q=Q, nx=n, ny=n, nz=n if Q == 27 else 1, nu=0.01, storage="f64",
+               collision=collision, trace_in_s=trace_in_s)
+    s.init_fields(rho, u)
+    s.step(steps)
+    d = oracle_run(Q, n, 0.01, rho, u, steps, collision=1 if collision == "lbgk" else 0,
+                   trace_in_s=trace_in_s)
+    err = np.max(np.abs(s.get_populations() - d.get_populations()))
+    say("  max |df| = %.3e" % err)
+    assert err < 1e-13
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_one_step_f32(Q):
+    n = 16
+    say("case: one step F32 Q=%d n=%d" % (Q, n))
+    if Q == 27:
+        rho, u, _ = W.taylor_green_3d(n, re=200.0, ma=0.2, perturb=0.05, seed=5)
+    else:
+        rho, u = W.taylor_green_2d(n, 0.06)
+    s = solver(Q=Q, nx=n, ny=n, nz=n if Q == 27 else 1, nu=0.005, storage="f32")
+    s.init_fields(rho, u)
+    f0 = s.get_populations()
+    d = oracle.Domain(Q, n, n, n if Q == 27 else 1, 0.005)
+    d.init_fields(rho, u)
+    assert np.max(np.abs(f0 - d.get_populations())) < 1e-8   # FP32 shifted storage of f^eq
+    s.step(1)
+    d.step(1)
+    w = lattice_w(Q)[:, None]
+    ratio = np.max(np.abs(s.get_populations() - d.get_populations()) / w)
+    say("  one-step max |df| / W_i = %.3e" % ratio)
+    assert ratio < 1e-6
+
+
+def test_cfg1_tg2d_64_f64_analytic_and_oracle():
+    """D2Q9 KBC Taylor-Green 64x64, FP64, u0=0.02, nu=0.01, 500 steps."""
+    n, nu, steps = 64, 0.01, 500
+    say("case: D2Q9 TG 64^2 F64 500 steps")
+    rho, u = W.taylor_green_2d(n, 0.02)
+    s = solver(Q=9, nx=n, ny=n, nz=1, nu=nu, storage="f64")
+    s.init_fields(rho, u)
+    s.step(steps)
+    _, ug, tg = s.moments()
+    ref = u * W.taylor_green_2d_decay(nu, n, steps)
+    err_an = np.linalg.norm(ug - ref) / np.linalg.norm(ref)
+    d = oracle_run(9, n, nu, rho, u, steps)
+    _, uo, _ = d.moments()
+    err_or = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    say("  vs analytic %.3e  vs oracle %.3e  mass drift %.3e" % (err_an, err_or,
+                                                                 tg["mass"] - rho.sum()))
+    assert err_an <= 2.5e-3
+    assert err_or <= 1e-12
+    assert abs(tg["mass"] - rho.sum()) < 1e-10
+    assert np.all(np.abs(tg["momentum"]) < 1e-10)
+
+
+@pytest.mark.slow
+def test_tg3d_32_f32_1000_steps_within_tolerance():
+    """D3Q27 KBC TG at Re=1600, Ma=0.1 on 32^3 for 1000 steps: FP32 against the
+    FP64 oracle, velocity rel L2 <= 1e-5."""
+    n, steps = 32, 1000
+    say("case: D3Q27 TG 32^3 F32 Re=1600 1000 steps")
+    rho, u, nu = W.taylor_green_3d(n)
+    s = solver(Q=27, nx=n, ny=n, nz=n, nu=nu, storage="f32")
+    s.init_fields(rho, u)
+    d = oracle.Domain(27, n, n, n, nu)
+    d.init_fields(rho, u)
+    errs = {}
+    for mark in (100, 1000):
+        s.step(mark - s.info()["step"])
+        d.step(mark - d.time)
+        _, ug, _ = s.moments()
+        _, uo, _ = d.moments()
+        errs[mark] = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    say("  F32 velocity rel L2: step 100 %.3e, step 1000 %.3e" % (errs[100], errs[1000]))
+    assert errs[1000] <= 1e-5
+
+
+@pytest.mark.parametrize("storage,mode", [("f16", "f16"), ("bf16", "bf16")])
+def test_16bit_storage_one_step_within_one_ulp(storage, mode):
+    n = 16
+    say("case: one step %s D3Q27 n=%d" % (storage, n))
+    rho, u, nu = W.taylor_green_3d(n, re=400.0, ma=0.1, perturb=1e-3, seed=6)
+    s = solver(Q=27, nx=n, ny=n, nz=n, nu=nu, storage=storage)
+    s.init_fields(rho, u)
+    d = oracle.Domain(27, n, n, n, nu, storage=mode)
+    d.init_fields(rho, u)
+    w = lattice_w(27)[:, None]
+    g0, o0 = s.get_populations() - w, d.get_populations() - w
+    s.step(1)
+    d.step(1)
+    g, o = s.get_populations() - w, d.get_populations() - w
+    # storage ulp of each oracle value
+    p = 11 if mode == "f16" else 8
+    emin = -14 if mode == "f16" else -126
+    e = np.maximum(np.floor(np.log2(np.maximum(np.abs(o), 1e-300))), emin)
+    ulp = np.maximum(2.0 ** (e - p + 1), 1e-6 * w)
+    k = np.abs(g - o) / ulp
+    frac1 = np.mean(k <= 1.0 + 1e-9)
+    say("  init max ulp diff %.1f; step 1: max %.1f ulp, share within 1 ulp %.5f"
+        % (np.max(np.abs(g0 - o0) / ulp), k.max(), frac1))
+    assert frac1 >= 0.999
+    assert k.max() <= 2.0 + 1e-9
+
+
+def test_full_size_256_sampled_one_step_f32():
+    """Launch configuration of the benchmark (D3Q27 TG 256^3, FP32): one step,
+    sampled nodes recomputed one by one by the oracle from the same inputs."""
+    from paper_1710_02375_amd import lbm
+
+    n = 256
+    say("case: D3Q27 TG 256^3 F32 one step, sampled parity")
+    rho, u, nu = W.taylor_green_3d(n)
+    s = lbm.Solver([dict(Q=27, nx=n, ny=n, nz=n, nu=nu, storage="f32")])
+    s.init_fields(rho, u)
+    s.step(1)
+    fg = s.get_populations()
+    c, w = oracle.lattice(27)
+    rng = np.random.default_rng(256)
+    pts = list(rng.integers(0, n, size=(200, 3))) + [np.array([0, 0, 0]), np.array([n - 1] * 3),
+                                                      np.array([0, n - 1, 17])]
+    beta = 1.0 / (6 * nu + 1)
+    worst = 0.0
+    for x, y, z in pts:
+        f = np.zeros(27)
+        for i in range(27):
+            sx, sy, sz = (x - c[i, 0]) % n, (y - c[i, 1]) % n, (z - c[i, 2]) % n
+            m = sx + n * (sy + n * sz)
+            f[i] = oracle.equilibrium(27, rho[m], u[:, m])[i]
+        fo, _, _ = oracle.collide(27, beta, f)
+        node = x + n * (y + n * z)
+        worst = max(worst, np.max(np.abs(fg[:, node] - fo) / w))
+    say("  sampled max |df| / W_i = %.3e over %d nodes" % (worst, len(pts)))
+    assert worst < 1e-6
+    # conservation over the whole grid
+    _, _, tot = s.moments(fields=False)
+    assert abs(tot["mass"] - rho.sum()) < 1e-6 * rho.sum() * 1e-3
+
+
+def test_graph_replay_equals_eager_and_runs_are_deterministic():
+    from paper_1710_02375_amd import lbm
+
+    n = 24
+    say("case: graph vs eager, determinism, D3Q27 F32 n=%d" % n)
+    rho, u, nu = W.taylor_green_3d(n, re=800.0, perturb=1e-3, seed=8)
+    outs = []
+    for use_graph in (True, False, True):
+        s = lbm.Solver([dict(Q=27, nx=n, ny=n, nz=n, nu=nu, storage="f32")], use_graph=use_graph)
+        s.init_fields(rho, u)
+        for _ in range(3):
+            s.step(7)
+            s.synchronize()
+        outs.append(s.get_populations())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+
+
+def test_checkpoint_resume_is_bitwise():
+    from paper_1710_02375_amd import lbm
+
+    n = 16
+    say("case: checkpoint/resume D3Q27 F16 n=%d" % n)
+    rho, u, nu = W.taylor_green_3d(n, re=800.0, perturb=1e-3, seed=9)
+    desc = dict(Q=27, nx=n, ny=n, nz=n, nu=nu, storage="f16")
+    a = lbm.Solver([desc])
+    a.init_fields(rho, u)
+    a.step(10)
+    ck = a.get_populations()
+    a.step(10)
+    ref = a.get_populations()
+    a.close()
+    b = lbm.Solver([desc])
+    b.set_populations(ck)
+    assert np.array_equal(b.get_populations(), ck)
+    b.step(10)
+    assert np.array_equal(b.get_populations(), ref)
+
+
+def test_nonfinite_state_reported():
+    from paper_1710_02375_amd import lbm
+
+    n = 8
+    say("case: NaN injection D3Q27 F32")
+    s = lbm.Solver([dict(Q=27, nx=n, ny=n, nz=n, nu=0.05, storage="f32")])
+    f = s.get_populations()
+    f[5, 100] = np.nan
+    s.set_populations(f)
+    s.step(2)
+    with pytest.raises(lbm.LBMError) as ei:
+        s.synchronize()
+    assert ei.value.status == lbm.LBM_ERR_NONFINITE
+    _, _, tot = s.moments()
+    assert tot["status"] == lbm.LBM_ERR_NONFINITE
+
+
+def test_gamma_statistics_and_torch_allocator():
+    import torch
+
+    from paper_1710_02375_amd import lbm
+
+    n = 16
+    say("case: stats + torch allocator/stream D3Q27 F32")
+    rho, u, nu = W.taylor_green_3d(n, re=1600.0, perturb=1e-3, seed=10)
+    alloc = lbm.TorchAllocator(0)
+    st = torch.cuda.Stream()
+    s = lbm.Solver([dict(Q=27, nx=n, ny=n, nz=n, nu=nu, storage="f32")], stream=st,
+                   allocator=alloc)
+    s.set_stats(True)
+    s.init_fields(rho, u)
+    s.step(5)
+    _, ug, tot = s.moments()
+    d = oracle_run(27, n, nu, rho, u, 5)
+    _, uo, to = d.moments()
+    say("  gamma gpu [%.4f %.4f %.4f] oracle [%.4f %.4f %.4f] fp64 share %.3f"
+        % (tot["gamma_min"], tot["gamma_mean"], tot["gamma_max"], to["gamma_min"],
+           to["gamma_mean"], to["gamma_max"], tot["fp64_gamma_fraction"]))
+    assert np.linalg.norm(ug - uo) / np.linalg.norm(uo) < 1e-6
+    assert abs(tot["gamma_mean"] - to["gamma_mean"]) < 1e-3
+    assert len(alloc._live) > 0
+    s.close()
