@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS and % HBM roofline, D3Q27 KBC, FP32 vs FP16-shifted at stated error"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bulk_d3q27_tg256_f32.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bulk_d3q27_tg256_f32.txt")
 
 
 def kernel_source_hash():
@@ -43,17 +43,19 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(nodes, launches_bytes):
-    """HBM bytes per launch from committed rocprofv3 counter runs, or None if
-    missing or taken on a different kernel source."""
+def read_traffic(nodes):
+    """HBM bytes per launch of the bulk kernel from the committed rocprofv3
+    counter summary (lines "key: value"), or None if it is missing, was taken
+    on a different kernel source, or on a different lattice size."""
     try:
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
+            kv = dict(l.split(":", 1) for l in f if ":" in l and not l.startswith("#"))
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        if kv.get("kernel_source_hash") != kernel_source_hash() or int(kv.get("nodes", 0)) != nodes:
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
         return None
-    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("nodes") != nodes:
-        return None
-    return t.get("hbm_bytes_per_launch")
 
 
 def copy_calibration(nbytes=1 << 31, reps=20):
@@ -82,7 +84,7 @@ def time_form(lbm, torch, n, storage, rho, u, nu, steps, warmup):
     stream = torch.cuda.Stream()
     s = lbm.Solver([dict(Q=27, nx=n, ny=n, nz=n, nu=nu, storage=storage)], stream=stream)
     s.init_fields(rho, u)
-    v = lbm.lbm_autotune(s.ctx, os.path.join(ROOT, "profiles", "autotune_cache.json"))
+    v = lbm.lbm_autotune(s.ctx, os.environ.get("KBC_AUTOTUNE_CACHE"))
     s.step(warmup)
     stream.synchronize()
     torch.cuda.synchronize()
@@ -121,6 +123,46 @@ def error_vs_f64(lbm, n, rho, u, nu, steps):
     return out
 
 
+def batched_form(lbm, torch, steps, warmup, count=64):
+    """64 uneven D2Q9 flap channels (seed 2375), FP32: aggregate MLUPS with one
+    launch per kernel per step for all instances, against one launch per
+    instance; the two final states must be bitwise equal."""
+    import workloads as W
+
+    chans = W.flap_channels(count=count, seed=2375)
+    descs = [dict(Q=9, nx=c["nx"], ny=c["ny"], nz=1, nu=c["nu"], storage="f32",
+                  faces=c["faces"], u_in=c["u_in"], inlet_profile=1) for c in chans]
+    total = sum(d["nx"] * d["ny"] for d in descs)
+    out = {}
+    finals = []
+    for mode, name in ((0, "batched"), (1, "per_instance")):
+        stream = torch.cuda.Stream()
+        s = lbm.Solver(descs, stream=stream)
+        for k, (c, d) in enumerate(zip(chans, descs)):
+            N = d["nx"] * d["ny"]
+            s.init_fields(np.ones(N), np.zeros((2, N)), inst=k)
+            s.set_body(*c["body"], inst=k)
+        s.set_launch_mode(mode)
+        s.step(warmup)
+        stream.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        s.step(steps)
+        ev1.record(stream)
+        stream.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"MLUPS": round(total * steps / el / 1e6, 1),
+                     "ms_per_step": round(el * 1e3 / steps, 5),
+                     "event_ms_per_step": round(ev0.elapsed_time(ev1) / steps, 5)}
+        finals.append([s.get_populations(k) for k in (0, count // 2, count - 1)])
+        s.close()
+    out["nodes"] = total
+    out["bytes_per_lattice_update"] = 72
+    out["bitwise_equal"] = all(np.array_equal(a, b) for a, b in zip(*finals))
+    return out
+
+
 def cpu_baseline(seconds=12.0):
     """The oracle as it stands, on a bounded sample of the workload."""
     import oracle
@@ -154,6 +196,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--error-steps", type=int, default=100)
+    ap.add_argument("--batched-steps", type=int, default=1000)
+    ap.add_argument("--batched-warmup", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -174,7 +218,7 @@ def main():
     mlups, ms, kms, info = time_form(lbm, torch, n, "f32", rho, u, nu, args.steps, args.warmup)
     bytes_per_lup = info["bytes_per_update"]
     achieved = bytes_per_lup * n ** 3 / (kms * 1e-3) / 1e9
-    traffic = read_traffic(n ** 3, bytes_per_lup * n ** 3)
+    traffic = read_traffic(n ** 3)
     result = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
@@ -199,6 +243,8 @@ def main():
                                          "frac": round(a2 / HBM_PEAK_GBS, 4),
                                          "bytes_per_lattice_update": i2["bytes_per_update"],
                                          "variant": i2["variant"]}
+        var["batched_d2q9_flap_channels_f32"] = batched_form(lbm, torch, args.batched_steps,
+                                                             args.batched_warmup)
         err = error_vs_f64(lbm, n, rho, u, nu, args.error_steps)
         var["velocity_rel_l2_vs_f64_at_step_%d" % args.error_steps] = err
         result["variants"] = var

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -18,6 +19,9 @@
 #include "kernels.hpp"
 
 using namespace kbc;
+
+// Workgroups of the FP64 pass over deferred near-equilibrium nodes.
+static constexpr int kFixupBlocks = 512;
 
 struct lbm_ctx {
   int device = 0;
@@ -47,6 +51,8 @@ struct lbm_ctx {
   int64_t* dclock = nullptr;
   uint32_t* derr = nullptr;
   uint32_t* herr = nullptr;       // pinned mirror of the error word
+  uint32_t* dneq_count = nullptr; // deferred near-equilibrium nodes of a step
+  uint2* dneq_list = nullptr;
   hipEvent_t err_event = nullptr;
   bool err_pending = false;
   int64_t step = 0;
@@ -226,6 +232,18 @@ void push_box_tiles(std::vector<BoxTile>& out, int region, const Region& r) {
   }
 }
 
+// Statistics slots: bulk tiles, boundary tiles, then the FP64-pass workgroups.
+lbm_status ensure_stats(lbm_ctx* c) {
+  const size_t need = c->tiles.size() + c->btiles.size() + kFixupBlocks + 1;
+  if (need <= c->dstats_cap) return LBM_OK;
+  dev_free(c, c->dstats);
+  c->dstats = nullptr;
+  lbm_status st = dev_alloc(c, need * sizeof(StatPartial), (void**)&c->dstats);
+  if (st) return st;
+  c->dstats_cap = need;
+  return LBM_OK;
+}
+
 // Rebuilds regions, boundary and geometry work lists, and the stats buffer.
 lbm_status rebuild_work(lbm_ctx* c) {
   c->regions.clear();
@@ -279,13 +297,7 @@ lbm_status rebuild_work(lbm_ctx* c) {
   if ((st = upload(c, &c->dregions, c->regions))) return st;
   if ((st = upload(c, &c->dbtiles, c->btiles))) return st;
   if ((st = upload(c, &c->dgtiles, c->gtiles))) return st;
-  const size_t need = c->tiles.size() + c->btiles.size() + 1;
-  if (need > c->dstats_cap) {
-    dev_free(c, c->dstats);
-    c->dstats = nullptr;
-    if ((st = dev_alloc(c, need * sizeof(StatPartial), (void**)&c->dstats))) return st;
-    c->dstats_cap = need;
-  }
+  if ((st = ensure_stats(c))) return st;
   invalidate_graphs(c);
   return LBM_OK;
 }
@@ -309,13 +321,7 @@ lbm_status rebuild_tiles(lbm_ctx* c) {
   }
   lbm_status st = upload(c, &c->dtiles, c->tiles);
   if (st) return st;
-  const size_t need = c->tiles.size() + c->btiles.size() + 1;
-  if (need > c->dstats_cap) {
-    dev_free(c, c->dstats);
-    c->dstats = nullptr;
-    if ((st = dev_alloc(c, need * sizeof(StatPartial), (void**)&c->dstats))) return st;
-    c->dstats_cap = need;
-  }
+  if ((st = ensure_stats(c))) return st;
   invalidate_graphs(c);
   return LBM_OK;
 }
@@ -330,6 +336,9 @@ lbm_status enqueue_step(lbm_ctx* c, int src) {
   b.err = c->derr;
   b.clock = c->dclock;
   b.stats = c->stats_enabled ? c->dstats : nullptr;
+  b.neq_count = c->dneq_count;
+  b.neq_list = c->dneq_list;
+  b.neq_cap = (uint32_t)c->total_nodes;
   const int ngt = (int)c->gtiles.size();
   if (ngt > 0)
     for (int stage = 0; stage < 3; ++stage)
@@ -348,7 +357,8 @@ lbm_status enqueue_step(lbm_ctx* c, int src) {
                                c->stream));
     }
   }
-  if (c->time_dependent) HIPCHECK(c, launch_tick(c->dclock, c->stream));
+  HIPCHECK(c, c->ops->fixup(b, kFixupBlocks, ntiles + nbt, c->stream));
+  HIPCHECK(c, launch_step_end(c->dclock, c->dneq_count, c->time_dependent ? 1 : 0, c->stream));
   return LBM_OK;
 }
 
@@ -498,6 +508,8 @@ lbm_status lbm_destroy(lbm_ctx* c) {
   dev_free(c, c->dinst);
   dev_free(c, c->dclock);
   dev_free(c, c->derr);
+  dev_free(c, c->dneq_count);
+  dev_free(c, c->dneq_list);
   dev_free(c, c->dtiles);
   dev_free(c, c->dregions);
   dev_free(c, c->dbtiles);
@@ -583,13 +595,18 @@ lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_
   c->moving.assign(n_instances, 0);
   c->has_body.assign(n_instances, 0);
   c->force_valid.assign(n_instances, 0);
+  // Population arrays are padded so that consecutive arrays do not start a
+  // power of two apart (which maps the Q loads of a wave onto the same HBM
+  // channels); KBC_POP_PAD overrides the padding (elements, multiple of 64).
+  int64_t pad = 0;
+  if (const char* e = std::getenv("KBC_POP_PAD")) pad = std::max<int64_t>(0, std::atoll(e)) / 64 * 64;
   size_t off = 0, foff = 0;
   for (int k = 0; k < n_instances; ++k) {
     const lbm_instance_desc& d = desc[k];
     InstDev& I = c->hinst[k];
     std::memset(&I, 0, sizeof I);
     I.N = (int64_t)d.nx * d.ny * d.nz;
-    I.stride = (I.N + 63) / 64 * 64;
+    I.stride = (I.N + 63) / 64 * 64 + pad;
     I.pop_off = (int64_t)off;
     off += (size_t)Q * I.stride;
     I.flag_off = needs_flags(d) ? (int64_t)foff : -1;
@@ -602,6 +619,8 @@ lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_
     I.divy = make_fastdiv((uint32_t)d.ny);
     I.beta = 1.0 / (6.0 * d.nu + 1.0);
     I.beta_f = (float)I.beta;
+    I.near_eq = kNearEq;
+    if (const char* e = std::getenv("KBC_NEAR_EQ")) I.near_eq = (float)std::atof(e);
     I.collision = d.collision;
     I.trace_in_s = d.kbc_trace_in_s ? 1 : 0;
     I.inlet_profile = d.inlet_profile;
@@ -618,6 +637,8 @@ lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_
   if ((st = dev_alloc(c, foff, (void**)&c->flags))) return bail(st);
   if ((st = dev_alloc(c, sizeof(int64_t), (void**)&c->dclock))) return bail(st);
   if ((st = dev_alloc(c, sizeof(uint32_t), (void**)&c->derr))) return bail(st);
+  if ((st = dev_alloc(c, sizeof(uint32_t), (void**)&c->dneq_count))) return bail(st);
+  if ((st = dev_alloc(c, (size_t)c->total_nodes * sizeof(uint2), (void**)&c->dneq_list))) return bail(st);
   if (hipHostMalloc((void**)&c->herr, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
     fail(c, LBM_ERR_OOM, "hipHostMalloc failed");
     return bail(LBM_ERR_OOM);
@@ -632,7 +653,8 @@ lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_
       hipMemsetAsync(c->buf[1], 0, off * c->esize, c->stream) != hipSuccess ||
       hipMemsetAsync(c->flags, 0, foff, c->stream) != hipSuccess ||
       hipMemsetAsync(c->dclock, 0, sizeof(int64_t), c->stream) != hipSuccess ||
-      hipMemsetAsync(c->derr, 0, sizeof(uint32_t), c->stream) != hipSuccess) {
+      hipMemsetAsync(c->derr, 0, sizeof(uint32_t), c->stream) != hipSuccess ||
+      hipMemsetAsync(c->dneq_count, 0, sizeof(uint32_t), c->stream) != hipSuccess) {
     fail(c, LBM_ERR_DEVICE, "hipMemsetAsync failed");
     return bail(LBM_ERR_DEVICE);
   }
@@ -799,13 +821,18 @@ lbm_status lbm_moments(lbm_ctx* c, int inst, double* rho, double* u, lbm_totals*
   hipError_t e = c->ops->moments(c->dinst, inst, N, c->buf[c->cur], c->flags, dr, du, dp, &np, c->stream);
   if (e == hipSuccess) e = launch_reduce(dp, np, 4, dout, c->stream);
   double sums[4] = {0, 0, 0, 0};
-  StatPartial sp[2];
+  StatPartial sp[3];
   bool have_stats = false;
   if (e == hipSuccess && tot && c->stats_enabled && c->step > 0) {
     StatPartial* so = reinterpret_cast<StatPartial*>(dout + 8);
     e = launch_reduce_stats(c->dstats + c->tile_first[inst], c->tile_count[inst], so, c->stream);
     if (e == hipSuccess)
       e = launch_reduce_stats(c->dstats + c->tiles.size() + c->bt_first[inst], c->bt_count[inst], so + 1, c->stream);
+    // The FP64 pass serves all instances at once; its nodes are attributed
+    // to the instance only in single-instance contexts.
+    if (e == hipSuccess)
+      e = launch_reduce_stats(c->dstats + c->tiles.size() + c->btiles.size(),
+                              c->n_inst == 1 ? kFixupBlocks : 0, so + 2, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sp, so, sizeof sp, hipMemcpyDeviceToHost, c->stream);
     have_stats = true;
   }
@@ -823,12 +850,22 @@ lbm_status lbm_moments(lbm_ctx* c, int inst, double* rho, double* u, lbm_totals*
     for (int a = 0; a < 3; ++a) tot->momentum[a] = sums[1 + a];
     tot->gamma_min = tot->gamma_mean = tot->gamma_max = 2.0;
     if (have_stats) {
-      const uint64_t cnt = (uint64_t)sp[0].count + sp[1].count;
+      uint64_t cnt = 0, f64 = 0;
+      double gsum = 0.0;
+      float gmin = 1e30f, gmax = -1e30f;
+      for (int k = 0; k < 3; ++k) {
+        if (!sp[k].count) continue;
+        cnt += sp[k].count;
+        f64 += sp[k].fp64;
+        gsum += sp[k].gsum;
+        gmin = std::min(gmin, sp[k].gmin);
+        gmax = std::max(gmax, sp[k].gmax);
+      }
       if (cnt) {
-        tot->gamma_min = std::min(sp[0].count ? sp[0].gmin : 1e30f, sp[1].count ? sp[1].gmin : 1e30f);
-        tot->gamma_max = std::max(sp[0].count ? sp[0].gmax : -1e30f, sp[1].count ? sp[1].gmax : -1e30f);
-        tot->gamma_mean = (sp[0].gsum + sp[1].gsum) / (double)cnt;
-        tot->fp64_gamma_fraction = (double)(sp[0].fp64 + sp[1].fp64) / (double)cnt;
+        tot->gamma_min = gmin;
+        tot->gamma_max = gmax;
+        tot->gamma_mean = gsum / (double)cnt;
+        tot->fp64_gamma_fraction = (double)f64 / (double)cnt;
       }
     }
     tot->step = c->step;

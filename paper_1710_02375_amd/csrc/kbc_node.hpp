@@ -269,8 +269,6 @@ __device__ __noinline__ double gamma_fp64(const float (&d)[Q], double beta, int 
   return 1.0 / beta - (2.0 - 1.0 / beta) * a / b;
 }
 
-// Threshold on <Delta|Delta> below which the FP32 paths take gamma from FP64.
-constexpr float kNearEq = 1e-10f;
 
 struct CollideOut {
   float gamma;
@@ -289,9 +287,14 @@ struct CollideParams {
   R beta, inv_beta;
   double beta_d;
   int lbgk, trace_in_s;
+  float near_eq;
 };
 
-template <int Q, typename R>
+// DEFER = true: a near-equilibrium node of an FP32 path keeps the FP32 gamma
+// and reports out.fp64 = 1, so that the caller can redo it in FP64 later (the
+// bulk kernel does, to keep its register budget); DEFER = false computes the
+// FP64 gamma in place.
+template <int Q, typename R, bool DEFER = false>
 __device__ __forceinline__ bool collide(R (&d)[Q], const CollideParams<R>& P, CollideOut& out) {
   constexpr int D = dims<Q>();
   R rt, j[3];
@@ -338,7 +341,11 @@ __device__ __forceinline__ bool collide(R (&d)[Q], const CollideParams<R>& P, Co
       ss += ds[i] * ds[i] * inv;
     }
     const R dd = ss + R(2) * a + b;   // <Delta|Delta>
-    if (sizeof(R) == 4 && dd < R(kNearEq)) {
+    const bool near_eq = sizeof(R) == 4 && dd < R(P.near_eq);
+    if (near_eq && DEFER) {
+      out.fp64 = 1;
+      if (b > R(0)) gamma = P.inv_beta - (R(2) - P.inv_beta) * a * frcp(b);
+    } else if (near_eq) {
       float tmp[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) tmp[i] = (float)d[i];

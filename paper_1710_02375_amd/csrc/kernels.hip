@@ -405,7 +405,8 @@ __device__ void block_stats(float gmin, float gmax, double gsum, uint32_t cnt, u
 // ---------------------------------------------------------------------------
 // Bulk kernel: fused pull-stream + collide, one thread per node.
 // ---------------------------------------------------------------------------
-template <int Q, int ST, int BLOCK, int WAVES, bool STATS>
+// MEM bit 0: non-temporal stores; bit 1: non-temporal loads.
+template <int Q, int ST, int BLOCK, int WAVES, int MEM, bool STATS>
 __global__ void __launch_bounds__(BLOCK, WAVES)
     k_bulk(StepBuffers b, const Tile* __restrict__ tiles, int tile0) {
   using S = Store<ST>;
@@ -413,7 +414,9 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
   using R = typename S::R;
   const int ti = tile0 + blockIdx.x;
   const Tile tl = tiles[ti];
-  const InstDev& I = b.insts[tl.inst];
+  // Local copy: read once, not re-read after every store (the compiler cannot
+  // prove the descriptor does not alias the populations).
+  const InstDev I = b.insts[tl.inst];
   const int nx = I.nx, ny = I.ny;
   const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
   const int64_t stride = I.stride;
@@ -426,6 +429,7 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
   P.beta_d = I.beta;
   P.lbgk = I.collision;
   P.trace_in_s = I.trace_in_s;
+  P.near_eq = I.near_eq;
   float gmin = 1e30f, gmax = -1e30f;
   double gsum = 0.0;
   uint32_t cnt = 0, f64 = 0;
@@ -445,24 +449,47 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
       zm = (uint32_t)(c.z == 0 ? nz - 1 : c.z - 1) * plane;
       zp = (uint32_t)(c.z == nz - 1 ? 0 : c.z + 1) * plane;
     }
-    R f[Q];
+    T raw[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const uint32_t sx = cx(i) == 0 ? (uint32_t)c.x : (cx(i) > 0 ? xm : xp);
       const uint32_t sy = cy(i) == 0 ? y0 : (cy(i) > 0 ? ym : yp);
       const uint32_t sz = cz<Q>(i) == 0 ? z0 : (cz<Q>(i) > 0 ? zm : zp);
-      f[i] = S::dec(sb[i * stride + (sx + sy + sz)]);
+      const T* p = sb + (i * stride + (sx + sy + sz));
+      raw[i] = (MEM & 2) ? __builtin_nontemporal_load(p) : *p;
     }
-    CollideOut co;
-    if (!collide<Q, R>(f, P, co)) atomicOr(b.err, 1u);
+    // All Q loads are issued before the first use: without this fence the
+    // scheduler consumes each value right after its load and a wave keeps a
+    // single load in flight.
+    __builtin_amdgcn_sched_barrier(0);
+    R f[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) db[i * stride + node] = S::enc(f[i]);
-    if (STATS) {
+    for (int i = 0; i < Q; ++i) f[i] = S::dec(raw[i]);
+    CollideOut co;
+    if (!collide<Q, R, true>(f, P, co)) atomicOr(b.err, 1u);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      T* p = db + (i * stride + node);
+      if (MEM & 1) __builtin_nontemporal_store(S::enc(f[i]), p); else *p = S::enc(f[i]);
+    }
+    // Near-equilibrium nodes go to the FP64 pass; one atomic per wave.
+    const uint64_t m = __ballot(co.fp64 != 0);
+    if (m) {
+      const int lane = threadIdx.x & 63;
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(b.neq_count, (uint32_t)__popcll(m));
+      base = __shfl(base, leader);
+      if (co.fp64) {
+        const uint32_t slot = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        if (slot < b.neq_cap) b.neq_list[slot] = make_uint2((uint32_t)tl.inst, node);
+      }
+    }
+    if (STATS && !co.fp64) {
       gmin = fminf(gmin, co.gamma);
       gmax = fmaxf(gmax, co.gamma);
       gsum += co.gamma;
       cnt += 1;
-      f64 += co.fp64;
     }
   }
   if (STATS) block_stats<BLOCK>(gmin, gmax, gsum, cnt, f64, b.stats + ti);
@@ -505,6 +532,7 @@ __global__ void __launch_bounds__(256) k_boundary(StepBuffers b, const Region* _
   P.beta_d = I.beta;
   P.lbgk = I.collision;
   P.trace_in_s = I.trace_in_s;
+  P.near_eq = I.near_eq;
   float gmin = 1e30f, gmax = -1e30f;
   double gsum = 0.0;
   uint32_t cnt = 0, f64 = 0;
@@ -599,6 +627,60 @@ __global__ void __launch_bounds__(256) k_geometry(int stage, const InstDev* __re
     }
     fl[node] = (uint8_t)((fv & (FLAG_STATIC | FLAG_SOLID_NEXT)) | (solid ? FLAG_SOLID : 0) |
                          (cut ? FLAG_BODY : 0));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64-gamma pass over the near-equilibrium nodes deferred by the bulk kernel:
+// the node is streamed and collided again from the same source state, with
+// gamma from FP64, and its output overwritten.
+// ---------------------------------------------------------------------------
+template <int Q, int ST>
+__global__ void __launch_bounds__(256) k_neq_fixup(StepBuffers b, int stat0) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  using R = typename S::R;
+  const uint32_t n = min(*b.neq_count, b.neq_cap);
+  float gmin = 1e30f, gmax = -1e30f;
+  double gsum = 0.0;
+  uint32_t cnt = 0, f64 = 0;
+  for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+    const uint2 e = b.neq_list[k];
+    const InstDev& I = b.insts[e.x];
+    const T* sb = static_cast<const T*>(b.src) + I.pop_off;
+    T* db = static_cast<T*>(b.dst) + I.pop_off;
+    const Coord c = node_coord(I, e.y);
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      uint32_t m;
+      resolve_nb(I, c.x, c.y, c.z, -cx(i), -cy(i), -cz<Q>(i), m);
+      f[i] = S::dec(sb[i * I.stride + m]);
+    }
+    CollideParams<R> P;
+    P.beta = (R)I.beta;
+    P.inv_beta = (R)(1.0 / I.beta);
+    P.beta_d = I.beta;
+    P.lbgk = I.collision;
+    P.trace_in_s = I.trace_in_s;
+    P.near_eq = I.near_eq;
+    CollideOut co;
+    if (!collide<Q, R, false>(f, P, co)) atomicOr(b.err, 1u);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) db[i * I.stride + e.y] = S::enc(f[i]);
+    gmin = fminf(gmin, co.gamma);
+    gmax = fmaxf(gmax, co.gamma);
+    gsum += co.gamma;
+    cnt += 1;
+    f64 += 1;
+  }
+  if (b.stats) block_stats<256>(gmin, gmax, gsum, cnt, f64, b.stats + stat0 + blockIdx.x);
+}
+
+__global__ void k_step_end(int64_t* clock, uint32_t* neq_count, int tick) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *neq_count = 0u;
+    if (tick) clock[0] += 1;
   }
 }
 
@@ -835,10 +917,6 @@ __global__ void __launch_bounds__(256) k_force(const InstDev* __restrict__ insts
 // ---------------------------------------------------------------------------
 // Clock and reductions
 // ---------------------------------------------------------------------------
-__global__ void k_tick(int64_t* clock) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] += 1;
-}
-
 __global__ void __launch_bounds__(256) k_reduce(const double* partials, int n, int width,
                                                 double* out) {
   // Fixed order: thread t sums partials t, t+256, ... sequentially, then a
@@ -878,13 +956,18 @@ __global__ void k_reduce_stats(const StatPartial* parts, int n, StatPartial* out
 // ---------------------------------------------------------------------------
 struct BulkVariant {
   const char* name;
-  int block, tile, waves;
+  int block, tile, waves, mem;
 };
 
+// Workgroup size, nodes per tile (a workgroup loops over its tile), minimum
+// waves per SIMD requested from the register allocator, non-temporal access.
 static const BulkVariant kVariants[] = {
-    {"b256_t256_w1", 256, 256, 1},  {"b256_t512_w1", 256, 512, 1},
-    {"b128_t128_w1", 128, 128, 1},  {"b512_t512_w1", 512, 512, 1},
-    {"b256_t256_w2", 256, 256, 2},  {"b256_t1024_w2", 256, 1024, 2},
+    {"b256_t256_w1", 256, 256, 1, 0},         {"b256_t512_w1", 256, 512, 1, 0},
+    {"b128_t128_w1", 128, 128, 1, 0},         {"b512_t512_w1", 512, 512, 1, 0},
+    {"b256_t256_w2", 256, 256, 2, 0},         {"b256_t1024_w2", 256, 1024, 2, 0},
+    {"b512_t512_w1_nts", 512, 512, 1, 1},     {"b256_t256_w2_nts", 256, 256, 2, 1},
+    {"b256_t1024_w2_nts", 256, 1024, 2, 1},   {"b512_t512_w1_ntls", 512, 512, 1, 3},
+    {"b256_t1024_w2_ntls", 256, 1024, 2, 3},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -892,16 +975,16 @@ int bulk_variant_count() { return kNumVariants; }
 const char* bulk_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVariants[v].name : "?"; }
 int bulk_variant_tile(int v) { return kVariants[(v >= 0 && v < kNumVariants) ? v : 0].tile; }
 
-template <int Q, int ST, int BLOCK, int WAVES>
+template <int Q, int ST, int BLOCK, int WAVES, int MEM>
 static hipError_t launch_bulk_v(const StepBuffers& b, const Tile* tiles, int tile0, int ntiles,
                                 hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (b.stats)
-    hipLaunchKernelGGL((k_bulk<Q, ST, BLOCK, WAVES, true>), dim3(ntiles), dim3(BLOCK), 0, s, b,
-                       tiles, tile0);
+    hipLaunchKernelGGL((k_bulk<Q, ST, BLOCK, WAVES, MEM, true>), dim3(ntiles), dim3(BLOCK), 0, s,
+                       b, tiles, tile0);
   else
-    hipLaunchKernelGGL((k_bulk<Q, ST, BLOCK, WAVES, false>), dim3(ntiles), dim3(BLOCK), 0, s, b,
-                       tiles, tile0);
+    hipLaunchKernelGGL((k_bulk<Q, ST, BLOCK, WAVES, MEM, false>), dim3(ntiles), dim3(BLOCK), 0, s,
+                       b, tiles, tile0);
   return hipGetLastError();
 }
 
@@ -909,12 +992,17 @@ template <int Q, int ST>
 static hipError_t launch_bulk(int v, const StepBuffers& b, const Tile* tiles, int tile0,
                               int ntiles, hipStream_t s) {
   switch (v) {
-    case 1: return launch_bulk_v<Q, ST, 256, 1>(b, tiles, tile0, ntiles, s);
-    case 2: return launch_bulk_v<Q, ST, 128, 1>(b, tiles, tile0, ntiles, s);
-    case 3: return launch_bulk_v<Q, ST, 512, 1>(b, tiles, tile0, ntiles, s);
-    case 4: return launch_bulk_v<Q, ST, 256, 2>(b, tiles, tile0, ntiles, s);
-    case 5: return launch_bulk_v<Q, ST, 256, 2>(b, tiles, tile0, ntiles, s);
-    default: return launch_bulk_v<Q, ST, 256, 1>(b, tiles, tile0, ntiles, s);
+    case 1: return launch_bulk_v<Q, ST, 256, 1, 0>(b, tiles, tile0, ntiles, s);
+    case 2: return launch_bulk_v<Q, ST, 128, 1, 0>(b, tiles, tile0, ntiles, s);
+    case 3: return launch_bulk_v<Q, ST, 512, 1, 0>(b, tiles, tile0, ntiles, s);
+    case 4: return launch_bulk_v<Q, ST, 256, 2, 0>(b, tiles, tile0, ntiles, s);
+    case 5: return launch_bulk_v<Q, ST, 256, 2, 0>(b, tiles, tile0, ntiles, s);
+    case 6: return launch_bulk_v<Q, ST, 512, 1, 1>(b, tiles, tile0, ntiles, s);
+    case 7: return launch_bulk_v<Q, ST, 256, 2, 1>(b, tiles, tile0, ntiles, s);
+    case 8: return launch_bulk_v<Q, ST, 256, 2, 1>(b, tiles, tile0, ntiles, s);
+    case 9: return launch_bulk_v<Q, ST, 512, 1, 3>(b, tiles, tile0, ntiles, s);
+    case 10: return launch_bulk_v<Q, ST, 256, 2, 3>(b, tiles, tile0, ntiles, s);
+    default: return launch_bulk_v<Q, ST, 256, 1, 0>(b, tiles, tile0, ntiles, s);
   }
 }
 
@@ -989,10 +1077,17 @@ static hipError_t launch_force(const InstDev* insts, int inst, const void* prev,
 }
 
 template <int Q, int ST>
+static hipError_t launch_fixup(const StepBuffers& b, int nblocks, int stat0, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_neq_fixup<Q, ST>), dim3(nblocks), dim3(256), 0, s, b, stat0);
+  return hipGetLastError();
+}
+
+template <int Q, int ST>
 static const Ops* ops_for() {
-  static const Ops o = {launch_bulk<Q, ST>,     launch_boundary<Q, ST>, launch_geometry<Q, ST>,
-                        launch_init<Q, ST>,     launch_decode<Q, ST>,   launch_encode<Q, ST>,
-                        launch_moments<Q, ST>,  launch_force<Q, ST>};
+  static const Ops o = {launch_bulk<Q, ST>,    launch_boundary<Q, ST>, launch_geometry<Q, ST>,
+                        launch_init<Q, ST>,    launch_decode<Q, ST>,   launch_encode<Q, ST>,
+                        launch_moments<Q, ST>, launch_fixup<Q, ST>,    launch_force<Q, ST>};
   return &o;
 }
 
@@ -1015,8 +1110,8 @@ const Ops* get_ops(int Q, int storage) {
   return nullptr;
 }
 
-hipError_t launch_tick(int64_t* clock, hipStream_t s) {
-  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, clock);
+hipError_t launch_step_end(int64_t* clock, uint32_t* neq_count, int tick, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, s, clock, neq_count, tick);
   return hipGetLastError();
 }
 

@@ -30,6 +30,9 @@ struct StepBuffers {
   uint32_t* err;          // device error word
   const int64_t* clock;   // steps taken before this step
   StatPartial* stats;     // per-workgroup statistics, or null
+  uint32_t* neq_count;    // near-equilibrium nodes deferred to the FP64 pass
+  uint2* neq_list;        // (instance, node) of each deferred node
+  uint32_t neq_cap;
 };
 
 struct Ops {
@@ -61,6 +64,10 @@ struct Ops {
   hipError_t (*moments)(const InstDev* insts, int inst, int64_t N, const void* buf,
                         const uint8_t* flags, double* rho, double* u, double* partials,
                         int* nparts, hipStream_t s);
+  // Redoes the deferred near-equilibrium nodes with the FP64 gamma (grid of
+  // nblocks workgroups striding over the list); statistics go to
+  // stats[stat0 + workgroup].
+  hipError_t (*fixup)(const StepBuffers& b, int nblocks, int stat0, hipStream_t s);
   // Wall force (per point traction, per-workgroup partial force sums).
   hipError_t (*force)(const InstDev* insts, int inst, const void* prev, const uint8_t* flags,
                       const int64_t* clock, const double* xq, const double* nq,
@@ -75,7 +82,9 @@ int bulk_variant_count();
 const char* bulk_variant_name(int v);
 int bulk_variant_tile(int v);
 
-hipError_t launch_tick(int64_t* clock, hipStream_t s);
+// End of a step: clears the deferred-node count and, if tick, advances the
+// device clock.
+hipError_t launch_step_end(int64_t* clock, uint32_t* neq_count, int tick, hipStream_t s);
 // Sums `width` doubles over n partials in a fixed order into out[width].
 hipError_t launch_reduce(const double* partials, int n, int width, double* out, hipStream_t s);
 hipError_t launch_reduce_stats(const StatPartial* parts, int n, StatPartial* out, hipStream_t s);

@@ -105,7 +105,7 @@ struct Store<LBM_BF16_SHIFTED> {
   __device__ static T enc_d(double v) {
     uint64_t b = (uint64_t)__double_as_longlong(v);
     if ((b & 0x7fffffffffffffffull) >= 0x7ff0000000000000ull) return enc((float)v);
-    b = (b + 0x1fffffffffffull + ((b >> 45) & 1ull)) & ~0x1fffffffffffull;
+    b = (b + 0xfffffffffffull + ((b >> 45) & 1ull)) & ~0x1fffffffffffull;
     return (T)(__float_as_uint((float)__longlong_as_double((long long)b)) >> 16);
   }
 };
@@ -144,6 +144,10 @@ enum : uint8_t {
   FLAG_SPECIAL = FLAG_SOLID | FLAG_STATIC | FLAG_BODY,
 };
 
+// Default threshold on <Delta|Delta> below which the FP32 paths take gamma
+// from FP64.
+constexpr float kNearEq = 1e-10f;
+
 // Per-instance descriptor read by every kernel (device memory, one per
 // instance).  Populations of the instance live at buf + pop_off + i*stride.
 struct InstDev {
@@ -155,6 +159,7 @@ struct InstDev {
   FastDiv divx, divy;
   double beta;
   float beta_f;
+  float near_eq;      // <Delta|Delta> below which FP32 paths take gamma from FP64
   int collision;
   int trace_in_s;
   int inlet_profile;
