@@ -959,9 +959,19 @@ lbm_status lbm_set_launch_mode(lbm_ctx* c, int mode) {
   return LBM_OK;
 }
 
+// Whether every instance's population arrays fit in a 4 GiB window.
+static bool fits_off32(const lbm_ctx* c) {
+  for (const InstDev& I : c->hinst)
+    if ((uint64_t)c->Q * (uint64_t)I.stride * (uint64_t)c->esize >= (uint64_t(1) << 32)) return false;
+  return true;
+}
+
 lbm_status lbm_set_variant(lbm_ctx* c, int v) {
   if (!c) return LBM_ERR_INVALID;
   if (v < 0 || v >= bulk_variant_count()) return fail(c, LBM_ERR_INVALID, "variant %d out of range", v);
+  if (bulk_variant_off32(v) && !fits_off32(c))
+    return fail(c, LBM_ERR_UNSUPPORTED, "variant %s needs instances below 4 GiB of populations",
+                bulk_variant_name(v));
   if (v == c->variant) return LBM_OK;
   HIPCHECK(c, hipStreamSynchronize(c->stream));
   c->variant = v;
@@ -996,6 +1006,7 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int* chosen) {
   int best = c->variant;
   float best_ms = 1e30f;
   for (int v = 0; v < bulk_variant_count(); ++v) {
+    if (bulk_variant_off32(v) && !fits_off32(c)) continue;
     if ((st = lbm_set_variant(c, v))) break;
     if ((st = lbm_step(c, 2))) break;
     HIPCHECK(c, hipEventRecord(e0, c->stream));

@@ -294,14 +294,47 @@ struct CollideParams {
 // and reports out.fp64 = 1, so that the caller can redo it in FP64 later (the
 // bulk kernel does, to keep its register budget); DEFER = false computes the
 // FP64 gamma in place.
+//
+// The arithmetic follows the tensor-product structure of the lattice
+// (population index a + 3b + 9c for velocity (a-1, b-1, c-1)):
+//   - rho~ and j from 1-D sums along x, then y and z;
+//   - f^eq_i - W_i = rho p_x(a) p_y(b) p_z(c) - w_a w_b w_c with the 1-D
+//     equilibria p(c) = w(c)(1 + e(c)), built pairwise as deviations
+//     (rho folded into the x factor), no cancellation against W_i;
+//   - the second moments of Delta and its mass and momentum (for the
+//     conservation projection) from one reduction tree along z, y, x.
 template <int Q, typename R, bool DEFER = false>
 __device__ __forceinline__ bool collide(R (&d)[Q], const CollideParams<R>& P, CollideOut& out) {
   constexpr int D = dims<Q>();
+  constexpr int NR = Q / 3;   // x-rows: index b (2D) or b + 3c (3D)
+  constexpr int RST = rest<Q>();
+  // ---- moments (Eq. 5): sums along x, then over rows -----------------------
+  R srow[NR], jrow[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const R pm = d[3 * r + 2] + d[3 * r];
+    jrow[r] = d[3 * r + 2] - d[3 * r];
+    srow[r] = pm + d[3 * r + 1];
+  }
   R rt, j[3];
-  moments_dev<Q>(d, rt, j);
+  if (Q == 27) {
+    const R sb0 = srow[0] + srow[3] + srow[6];
+    const R sb1 = srow[1] + srow[4] + srow[7];
+    const R sb2 = srow[2] + srow[5] + srow[8];
+    rt = (sb0 + sb2) + sb1;
+    j[1] = sb2 - sb0;
+    j[2] = (srow[6] + srow[7] + srow[8]) - (srow[0] + srow[1] + srow[2]);
+    j[0] = ((jrow[0] + jrow[1] + jrow[2]) + (jrow[3] + jrow[4] + jrow[5])) +
+           (jrow[6] + jrow[7] + jrow[8]);
+  } else {
+    rt = (srow[0] + srow[2]) + srow[1];
+    j[1] = srow[2] - srow[0];
+    j[2] = R(0);
+    j[0] = (jrow[0] + jrow[2]) + jrow[1];
+  }
   const R rho = R(1) + rt;
   const R ir = frcp(rho);
-  R u[3] = {j[0] * ir, j[1] * ir, D == 3 ? j[2] * ir : R(0)};
+  const R u[3] = {j[0] * ir, j[1] * ir, j[2] * ir};
   const bool ok = rho > R(0) && u[0] < R(1) && u[0] > R(-1) && u[1] < R(1) && u[1] > R(-1) &&
                   u[2] < R(1) && u[2] > R(-1);
   if (!ok) {
@@ -309,37 +342,151 @@ __device__ __forceinline__ bool collide(R (&d)[Q], const CollideParams<R>& P, Co
     out.fp64 = 0;
     return false;
   }
+  // ---- per-axis equilibrium factors (Eqs. 4-5) -----------------------------
   AxisEq<R> A[3];
 #pragma unroll
   for (int a = 0; a < D; ++a) A[a] = axis_eq(u[a]);
   if (D == 2) A[2] = A[1];   // unused in 2D
-
-  R dh[Q];
+  const R wv[3] = {R(1.0 / 6.0), R(2.0 / 3.0), R(1.0 / 6.0)};
+  R ex[3] = {A[0].em, A[0].e0, A[0].ep};
+  R ey[3] = {A[1].em, A[1].e0, A[1].ep};
+  R ez[3] = {A[2].em, A[2].e0, A[2].ep};
+  // rho p_x - w, p_y, p_y - w, p_z, p_z - w
+  R dxr[3], py[3], dy[3], pz[3], dz[3];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) dh[i] = d[i] - R(weight<Q>(i)) * (rt + rho * eq_E<Q>(A, i));
-  const Shear<Q, R> S = shear_moments<Q>(dh);
-  const R ts = P.trace_in_s ? S.T : R(0);
-  R ds[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    ds[i] = shear_pop<Q>(S, i, ts);
-    dh[i] -= ds[i];
+  for (int k = 0; k < 3; ++k) {
+    dxr[k] = wv[k] * (rt + rho * ex[k]);
+    dy[k] = wv[k] * ey[k];
+    py[k] = wv[k] + dy[k];
+    dz[k] = wv[k] * ez[k];
+    pz[k] = wv[k] + dz[k];
   }
-  project_conserved<Q>(dh);
-
+  // ---- Delta = f~ - (f^eq - W) ---------------------------------------------
+  R dl[Q];
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const R dxy = dxr[a] * py[b] + wv[a] * dy[b];   // rho p_x p_y - w_a w_b
+      if (Q == 27) {
+        const R wab = R(w1d(a - 1) * w1d(b - 1));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int i = a + 3 * b + 9 * c;
+          dl[i] = d[i] - (dxy * pz[c] + wab * dz[c]);
+        }
+      } else {
+        const int i = a + 3 * b;
+        dl[i] = d[i] - dxy;
+      }
+    }
+  // ---- second moments, mass and momentum of Delta --------------------------
+  // m0/m1/m2: zeroth, first and second moment along z of each (a, b) column.
+  R m0[9], m1[9], m2[9];
+#pragma unroll
+  for (int ab = 0; ab < 9; ++ab) {
+    if (Q == 27) {
+      const R lo = dl[ab], mid = dl[ab + 9], hi = dl[ab + 18];
+      m2[ab] = hi + lo;
+      m1[ab] = hi - lo;
+      m0[ab] = m2[ab] + mid;
+    } else {
+      m0[ab] = dl[ab];
+      m1[ab] = R(0);
+      m2[ab] = R(0);
+    }
+  }
+  R n0[3], n1[3], n2[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    n2[a] = m0[a + 6] + m0[a];
+    n1[a] = m0[a + 6] - m0[a];
+    n0[a] = n2[a] + m0[a + 3];
+  }
+  const R Rm = (n0[0] + n0[2]) + n0[1];
+  const R Jx = n0[2] - n0[0];
+  const R Pxx = n0[2] + n0[0];
+  const R Jy = (n1[0] + n1[2]) + n1[1];
+  const R Pxy = n1[2] - n1[0];
+  const R Pyy = (n2[0] + n2[2]) + n2[1];
+  R Jz = R(0), Pxz = R(0), Pyz = R(0), Pzz = R(0);
+  if (Q == 27) {
+    R k0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) k0[a] = (m1[a] + m1[a + 6]) + m1[a + 3];
+    Jz = (k0[0] + k0[2]) + k0[1];
+    Pxz = k0[2] - k0[0];
+    Pyz = (m1[6] + m1[7] + m1[8]) - (m1[0] + m1[1] + m1[2]);
+    Pzz = ((m2[0] + m2[1] + m2[2]) + (m2[3] + m2[4] + m2[5])) + (m2[6] + m2[7] + m2[8]);
+  }
+  // Exact-conservation projection: mass and momentum that rounding left in
+  // Delta go to the rest and axis populations (columns of the inverse moment
+  // basis for rho and j); the second moments are unchanged by it.
+  dl[RST] -= Rm;
+  dl[RST + 1] -= R(0.5) * Jx;
+  dl[RST - 1] += R(0.5) * Jx;
+  dl[RST + 3] -= R(0.5) * Jy;
+  dl[RST - 3] += R(0.5) * Jy;
+  if (Q == 27) {
+    dl[RST + 9] -= R(0.5) * Jz;
+    dl[RST - 9] += R(0.5) * Jz;
+  }
+  // ---- shear part (Eqs. 2-3): deviatoric second moments --------------------
+  R T, Dxx, Dyy, Dzz;
+  if (Q == 27) {
+    T = Pxx + Pyy + Pzz;
+    const R t3 = T * R(1.0 / 3.0);
+    Dxx = Pxx - t3;
+    Dyy = Pyy - t3;
+    Dzz = -(Dxx + Dyy);
+  } else {
+    T = Pxx + Pyy;
+    Dxx = R(0.5) * (Pxx - Pyy);
+    Dyy = -Dxx;
+    Dzz = R(0);
+  }
+  const R ts = P.trace_in_s ? T : R(0);
+  const R tf = ts * R(0.5 / D);
+  const R Fx = R(0.5) * Dxx + tf, Fy = R(0.5) * Dyy + tf, Fz = R(0.5) * Dzz + tf;
+  const R Exy = R(0.25) * Pxy, Exz = R(0.25) * Pxz, Eyz = R(0.25) * Pyz;
+  auto ds_of = [&](int i) -> R {
+    const int n = nnz<Q>(i);
+    if (n == 1) return cx(i) != 0 ? Fx : (cy(i) != 0 ? Fy : Fz);
+    if (n == 2) {
+      const R e = (cx(i) != 0 && cy(i) != 0) ? Exy : (cx(i) != 0 ? Exz : Eyz);
+      const int sg = cx(i) * cy(i) + cx(i) * cz<Q>(i) + cy(i) * cz<Q>(i);
+      return sg > 0 ? e : -e;
+    }
+    if (n == 0) return -ts;
+    return R(0);
+  };
+  // ---- stabiliser gamma (Eq. 6) --------------------------------------------
   R gamma = R(2);
   out.fp64 = 0;
   if (!P.lbgk) {
+    const R gx[3] = {ir * A[0].gm, ir * A[0].g0, ir * A[0].gp};
+    const R gy[3] = {A[1].gm, A[1].g0, A[1].gp};
+    const R gz[3] = {A[2].gm, A[2].g0, A[2].gp};
     R a = R(0), b = R(0), ss = R(0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      R inv = ir * sel_g(A[0], cx(i)) * sel_g(A[1], cy(i));
-      if (Q == 27) inv *= sel_g(A[2], cz<Q>(i));
-      const R hi = dh[i] * inv;
-      b += hi * dh[i];
-      a += hi * ds[i];
-      ss += ds[i] * ds[i] * inv;
-    }
+    for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+      for (int aa = 0; aa < 3; ++aa) {
+        const R gxy = gx[aa] * gy[bb];
+#pragma unroll
+        for (int cc = 0; cc < (Q == 27 ? 3 : 1); ++cc) {
+          const int i = aa + 3 * bb + 9 * cc;
+          const R inv = (Q == 27) ? gxy * gz[cc] : gxy;   // 1 / f^eq_i
+          const R si = ds_of(i);
+          const R hi = dl[i] - si;                         // Delta h_i
+          const R hw = hi * inv;
+          b += hw * hi;
+          if (nnz<Q>(i) == 1 || nnz<Q>(i) == 2 || (nnz<Q>(i) == 0)) {
+            a += hw * si;
+            ss += si * si * inv;
+          }
+        }
+      }
     const R dd = ss + R(2) * a + b;   // <Delta|Delta>
     const bool near_eq = sizeof(R) == 4 && dd < R(P.near_eq);
     if (near_eq && DEFER) {
@@ -355,8 +502,16 @@ __device__ __forceinline__ bool collide(R (&d)[Q], const CollideParams<R>& P, Co
       gamma = P.inv_beta - (R(2) - P.inv_beta) * a * frcp(b);
     }
   }
+  // ---- post-collision state (Eqs. 1, 3): f - beta (2 Ds + gamma Dh) --------
+  const R bg = P.beta * gamma, b2 = R(2) * P.beta;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) d[i] -= P.beta * (R(2) * ds[i] + gamma * dh[i]);
+  for (int i = 0; i < Q; ++i) {
+    const R si = ds_of(i);
+    const int n = nnz<Q>(i);
+    const bool has_s = n == 1 || n == 2 || n == 0;
+    const R hi = has_s ? dl[i] - si : dl[i];
+    d[i] = has_s ? d[i] - bg * hi - b2 * si : d[i] - bg * hi;
+  }
   out.gamma = (float)gamma;
   return true;
 }

@@ -405,7 +405,10 @@ __device__ void block_stats(float gmin, float gmax, double gsum, uint32_t cnt, u
 // ---------------------------------------------------------------------------
 // Bulk kernel: fused pull-stream + collide, one thread per node.
 // ---------------------------------------------------------------------------
-// MEM bit 0: non-temporal stores; bit 1: non-temporal loads.
+// MEM bit 0: non-temporal stores; bit 1: non-temporal loads; bit 2: 32-bit
+// byte offsets from one base per instance (every instance's Q population
+// arrays span less than 4 GiB), which removes the 64-bit address arithmetic
+// and the per-population base registers.
 template <int Q, int ST, int BLOCK, int WAVES, int MEM, bool STATS>
 __global__ void __launch_bounds__(BLOCK, WAVES)
     k_bulk(StepBuffers b, const Tile* __restrict__ tiles, int tile0) {
@@ -450,13 +453,27 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
       zp = (uint32_t)(c.z == nz - 1 ? 0 : c.z + 1) * plane;
     }
     T raw[Q];
+    if (MEM & 4) {
+      constexpr uint32_t es = sizeof(T);
+      const uint32_t pstride = (uint32_t)stride * es;
+      const uint32_t bx[3] = {xp * es, (uint32_t)c.x * es, xm * es};   // by -cx + 1
+      const uint32_t byz[3] = {yp * es, y0 * es, ym * es};
+      const uint32_t bz[3] = {zp * es, z0 * es, zm * es};
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const uint32_t sx = cx(i) == 0 ? (uint32_t)c.x : (cx(i) > 0 ? xm : xp);
-      const uint32_t sy = cy(i) == 0 ? y0 : (cy(i) > 0 ? ym : yp);
-      const uint32_t sz = cz<Q>(i) == 0 ? z0 : (cz<Q>(i) > 0 ? zm : zp);
-      const T* p = sb + (i * stride + (sx + sy + sz));
-      raw[i] = (MEM & 2) ? __builtin_nontemporal_load(p) : *p;
+      for (int i = 0; i < Q; ++i) {
+        const uint32_t off = (uint32_t)i * pstride + bx[cx(i) + 1] + byz[cy(i) + 1] + bz[cz<Q>(i) + 1];
+        const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(sb) + off);
+        raw[i] = (MEM & 2) ? __builtin_nontemporal_load(p) : *p;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const uint32_t sx = cx(i) == 0 ? (uint32_t)c.x : (cx(i) > 0 ? xm : xp);
+        const uint32_t sy = cy(i) == 0 ? y0 : (cy(i) > 0 ? ym : yp);
+        const uint32_t sz = cz<Q>(i) == 0 ? z0 : (cz<Q>(i) > 0 ? zm : zp);
+        const T* p = sb + (i * stride + (sx + sy + sz));
+        raw[i] = (MEM & 2) ? __builtin_nontemporal_load(p) : *p;
+      }
     }
     // All Q loads are issued before the first use: without this fence the
     // scheduler consumes each value right after its load and a wave keeps a
@@ -469,7 +486,10 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
     if (!collide<Q, R, true>(f, P, co)) atomicOr(b.err, 1u);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      T* p = db + (i * stride + node);
+      T* p = (MEM & 4) ? reinterpret_cast<T*>(reinterpret_cast<char*>(db) +
+                                                ((uint32_t)i * (uint32_t)stride + node) *
+                                                    (uint32_t)sizeof(T))
+                       : db + (i * stride + node);
       if (MEM & 1) __builtin_nontemporal_store(S::enc(f[i]), p); else *p = S::enc(f[i]);
     }
     // Near-equilibrium nodes go to the FP64 pass; one atomic per wave.
@@ -967,13 +987,16 @@ static const BulkVariant kVariants[] = {
     {"b256_t256_w2", 256, 256, 2, 0},         {"b256_t1024_w2", 256, 1024, 2, 0},
     {"b512_t512_w1_nts", 512, 512, 1, 1},     {"b256_t256_w2_nts", 256, 256, 2, 1},
     {"b256_t1024_w2_nts", 256, 1024, 2, 1},   {"b512_t512_w1_ntls", 512, 512, 1, 3},
-    {"b256_t1024_w2_ntls", 256, 1024, 2, 3},
+    {"b256_t1024_w2_ntls", 256, 1024, 2, 3},  {"b512_t512_w1_nts_o32", 512, 512, 1, 5},
+    {"b256_t256_w2_nts_o32", 256, 256, 2, 5}, {"b256_t1024_w2_nts_o32", 256, 1024, 2, 5},
+    {"b256_t256_w1_o32", 256, 256, 1, 4},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int bulk_variant_count() { return kNumVariants; }
 const char* bulk_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVariants[v].name : "?"; }
 int bulk_variant_tile(int v) { return kVariants[(v >= 0 && v < kNumVariants) ? v : 0].tile; }
+bool bulk_variant_off32(int v) { return (kVariants[(v >= 0 && v < kNumVariants) ? v : 0].mem & 4) != 0; }
 
 template <int Q, int ST, int BLOCK, int WAVES, int MEM>
 static hipError_t launch_bulk_v(const StepBuffers& b, const Tile* tiles, int tile0, int ntiles,
@@ -1002,6 +1025,10 @@ static hipError_t launch_bulk(int v, const StepBuffers& b, const Tile* tiles, in
     case 8: return launch_bulk_v<Q, ST, 256, 2, 1>(b, tiles, tile0, ntiles, s);
     case 9: return launch_bulk_v<Q, ST, 512, 1, 3>(b, tiles, tile0, ntiles, s);
     case 10: return launch_bulk_v<Q, ST, 256, 2, 3>(b, tiles, tile0, ntiles, s);
+    case 11: return launch_bulk_v<Q, ST, 512, 1, 5>(b, tiles, tile0, ntiles, s);
+    case 12: return launch_bulk_v<Q, ST, 256, 2, 5>(b, tiles, tile0, ntiles, s);
+    case 13: return launch_bulk_v<Q, ST, 256, 2, 5>(b, tiles, tile0, ntiles, s);
+    case 14: return launch_bulk_v<Q, ST, 256, 1, 4>(b, tiles, tile0, ntiles, s);
     default: return launch_bulk_v<Q, ST, 256, 1, 0>(b, tiles, tile0, ntiles, s);
   }
 }

@@ -81,6 +81,9 @@ const Ops* get_ops(int Q, int storage);
 int bulk_variant_count();
 const char* bulk_variant_name(int v);
 int bulk_variant_tile(int v);
+// True if the variant addresses populations with 32-bit byte offsets from one
+// base per instance (requires Q * stride * sizeof(storage) < 2^32).
+bool bulk_variant_off32(int v);
 
 // End of a step: clears the deferred-node count and, if tick, advances the
 // device clock.
