@@ -29,6 +29,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FORM_TEXT = {"f32": "FP32 storage and arithmetic", "f64": "FP64 storage and arithmetic",
+             "f16": "FP16 storage of f - W with FP32 arithmetic",
+             "bf16": "BF16 storage of f - W with FP32 arithmetic"}
 METRIC = "MLUPS and % HBM roofline, D3Q27 KBC, FP32 vs FP16-shifted at stated error"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bulk_d3q27_tg256_f32.txt")
 
@@ -77,14 +80,20 @@ def copy_calibration(nbytes=1 << 31, reps=20):
                       "ms_per_copy": ms, "copy_GBs": 2 * nbytes / ms / 1e6}))
 
 
-def time_form(lbm, torch, n, storage, rho, u, nu, steps, warmup):
-    """MLUPS of one storage form; returns (mlups, ms_per_step, kernel_ms)."""
+def time_form(lbm, torch, n, storage, rho, u, nu, steps, warmup, variant=None):
+    """MLUPS of one storage form; returns (mlups, ms_per_step, kernel_ms, info).
+    variant: a bulk-kernel variant name, or None to autotune."""
     # A dedicated (default-priority) stream: the library launches on it and the
     # timing events are recorded on it.
     stream = torch.cuda.Stream()
     s = lbm.Solver([dict(Q=27, nx=n, ny=n, nz=n, nu=nu, storage=storage)], stream=stream)
     s.init_fields(rho, u)
-    v = lbm.lbm_autotune(s.ctx, os.environ.get("KBC_AUTOTUNE_CACHE"))
+    if variant:
+        names = [lbm.lbm_variant_name(k) for k in range(lbm.lbm_variant_count())]
+        v = names.index(variant)
+        lbm.lbm_set_variant(s.ctx, v)
+    else:
+        v = lbm.lbm_autotune(s.ctx, os.environ.get("KBC_AUTOTUNE_CACHE"))
     s.step(warmup)
     stream.synchronize()
     torch.cuda.synchronize()
@@ -163,6 +172,113 @@ def batched_form(lbm, torch, steps, warmup, count=64):
     return out
 
 
+def sphere_form(lbm, torch, storage, steps, sample_every, variant=None, dims=(512, 128, 128),
+                radius=16.0):
+    """Channel with the oscillating sphere (Re 300, Grad boundary nodes): MLUPS
+    over the stepping alone, then drag/lift coefficients every sample_every
+    steps from the wall force on an icosphere quadrature (5120 facets)."""
+    import math
+
+    import workloads as W
+
+    nx, ny, nz = dims
+    cfg = W.sphere_channel(nx, ny, nz, radius)
+    stream = torch.cuda.Stream()
+    s = lbm.Solver([dict(Q=27, nx=nx, ny=ny, nz=nz, nu=cfg["nu"], storage=storage,
+                         faces=cfg["faces"], u_in=cfg["u_in"], ramp_steps=cfg["ramp_steps"])],
+                   stream=stream)
+    N = nx * ny * nz
+    s.init_fields(np.ones(N), np.zeros((3, N)))
+    kind, p = cfg["body"]
+    s.set_body(kind, p)
+    if variant:
+        names = [lbm.lbm_variant_name(k) for k in range(lbm.lbm_variant_count())]
+        lbm.lbm_set_variant(s.ctx, names.index(variant))
+    else:
+        lbm.lbm_autotune(s.ctx, os.environ.get("KBC_AUTOTUNE_CACHE"))
+    U, R = cfg["U"], cfg["radius"]
+    norm = 0.5 * U * U * math.pi * R * R
+    series = []
+    t_step = 0.0
+    done = 0
+    while done < steps:
+        k = min(sample_every, steps - done)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        s.step(k)
+        stream.synchronize()
+        t_step += time.perf_counter() - t0
+        done += k
+        c = p[0:3] + p[4:7] * math.sin(p[7] * done + p[8])
+        xq, nq, wq = W.sphere_quadrature(c, R, subdiv=4)
+        F, _ = s.wall_force(xq, nq, wq)
+        series.append((done, F[0] / norm, F[1] / norm, F[2] / norm))
+    _, uu, tot = s.moments()
+    s.close()
+    return {"MLUPS": round(N * steps / t_step / 1e6, 1), "ms_per_step": round(t_step * 1e3 / steps, 5),
+            "series": series, "u": uu, "mass": tot["mass"]}
+
+
+def sphere_workload(lbm, torch, args):
+    """Config: D3Q27 channel 512x128x128, oscillating sphere R=16, Re=300;
+    FP32 and FP16-shifted against the FP64 form of the same kernel (itself
+    checked against the CPU oracle on a scaled copy in the test suite)."""
+    out = {}
+    ref = None
+    for storage in ("f64", "f32", "f16"):
+        r = sphere_form(lbm, torch, storage, args.sphere_steps, args.sphere_sample)
+        if ref is None:
+            ref = r
+        entry = {"MLUPS": r["MLUPS"], "ms_per_step": r["ms_per_step"],
+                 "Cd_Cl_last": [round(v, 6) for v in r["series"][-1][1:3]]}
+        if storage != "f64":
+            a, b = np.array(r["series"])[:, 1:3], np.array(ref["series"])[:, 1:3]
+            entry["force_coeff_max_abs_diff_vs_f64"] = float(np.max(np.abs(a - b)))
+            entry["velocity_rel_l2_vs_f64"] = float(np.linalg.norm(r["u"] - ref["u"]) /
+                                                    np.linalg.norm(ref["u"]))
+        out[storage] = entry
+    out["series_f64"] = [[int(t)] + [round(v, 6) for v in row] for t, *row in ref["series"]]
+    return {"metric": "MLUPS, drag/lift vs FP64", "unit": "MLUPS",
+            "config": {"workload": "D3Q27 KBC channel 512x128x128, oscillating sphere R=16 "
+                                   "(amplitude 4, period 3200), Re=300, Grad boundary nodes, "
+                                   "%d steps" % args.sphere_steps},
+            "forms": out}
+
+
+def tg512_workload(lbm, torch, args):
+    """Config: D3Q27 TG 512^3, Re=1600: MLUPS and HBM fraction per storage form,
+    velocity error of each against the FP64 form at steps 100 and 1000."""
+    import workloads as W
+
+    n = 512
+    rho, u, nu = W.taylor_green_3d(n)
+    forms = {}
+    for storage in ("f32", "f16", "bf16"):
+        m, ms, k, info = time_form(lbm, torch, n, storage, rho, u, nu, args.steps, args.warmup)
+        a = info["bytes_per_update"] * n ** 3 / (k * 1e-3) / 1e9
+        forms[storage] = {"MLUPS": round(m, 1), "ms_per_step": round(ms, 5),
+                          "achieved_GBs": round(a, 1), "frac": round(a / HBM_PEAK_GBS, 4),
+                          "variant": info["variant"]}
+    marks = (100, 1000)
+    fields = {}
+    for storage in ("f64", "f32", "f16", "bf16"):
+        s = lbm.Solver([dict(Q=27, nx=n, ny=n, nz=n, nu=nu, storage=storage)])
+        s.init_fields(rho, u)
+        done = 0
+        for mk in marks:
+            s.step(mk - done)
+            done = mk
+            _, uu, _ = s.moments()
+            fields[(storage, mk)] = uu if storage == "f64" else \
+                float(np.linalg.norm(uu - fields[("f64", mk)]) / np.linalg.norm(fields[("f64", mk)]))
+        s.close()
+    for storage in ("f32", "f16", "bf16"):
+        forms[storage]["velocity_rel_l2_vs_f64"] = {str(mk): fields[(storage, mk)] for mk in marks}
+    return {"metric": "MLUPS and % HBM roofline per storage form, error vs FP64", "unit": "MLUPS",
+            "config": {"workload": "D3Q27 KBC Taylor-Green 512^3 periodic, Re=1600, Ma=0.1"},
+            "forms": forms}
+
+
 def cpu_baseline(seconds=12.0):
     """The oracle as it stands, on a bounded sample of the workload."""
     import oracle
@@ -199,6 +315,12 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--batched-warmup", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--variant", default=None, help="bulk-kernel variant (default: autotune)")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64"])
+    ap.add_argument("--workload", default="tg256", choices=["tg256", "tg512", "sphere"],
+                    help="tg256 is the headline line; the others print their own line")
+    ap.add_argument("--sphere-steps", type=int, default=2000)
+    ap.add_argument("--sphere-sample", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus %d requested); the "
@@ -213,23 +335,31 @@ def main():
     import workloads as W
     from paper_1710_02375_amd import lbm
 
+    if args.workload == "sphere":
+        print(json.dumps(sphere_workload(lbm, torch, args)), flush=True)
+        return
+    if args.workload == "tg512":
+        print(json.dumps(tg512_workload(lbm, torch, args)), flush=True)
+        return
     n = args.n
     rho, u, nu = W.taylor_green_3d(n)
-    mlups, ms, kms, info = time_form(lbm, torch, n, "f32", rho, u, nu, args.steps, args.warmup)
+    mlups, ms, kms, info = time_form(lbm, torch, n, args.storage, rho, u, nu, args.steps,
+                                     args.warmup, args.variant)
     bytes_per_lup = info["bytes_per_update"]
     achieved = bytes_per_lup * n ** 3 / (kms * 1e-3) / 1e9
     traffic = read_traffic(n ** 3)
     result = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.storage,
         "data": "synthetic",
         "config": {"workload": "D3Q27 KBC Taylor-Green %d^3 periodic, Re=1600, Ma=0.1, "
-                               "1e-4 seeded perturbation, FP32 storage and arithmetic" % n,
+                               "1e-4 seeded perturbation, %s" % (n, FORM_TEXT[args.storage]),
                    "nodes": n ** 3, "bytes_per_lattice_update": bytes_per_lup},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "kbc::k_bulk<27, F32> (%s)" % info["variant"],
+                     "traffic": traffic if args.storage == "f32" else None,
+                     "kernel": "kbc::k_bulk<27, %s> (%s)" % (args.storage.upper(), info["variant"]),
                      "kernel_ms": round(kms, 5)},
     }
     if not args.no_variants:

@@ -219,3 +219,61 @@ def test_geometry_errors():
     with pytest.raises(lbm.LBMError) as ei:
         s.wall_force(np.zeros((1, 3)), np.array([[1.0, 0, 0]]), np.ones(1))
     assert ei.value.status == lbm.LBM_ERR_INVALID   # no step since set-up
+
+
+@pytest.mark.parametrize("storage,tol_f,tol_u", [("f64", 1e-12, 1e-12), ("f32", 5e-6, 1e-5),
+                                                  ("f16", 5e-2, 5e-3)])
+def test_sphere_channel_scaled_parity(storage, tol_f, tol_u):
+    """The sphere-channel workload at a quarter of its size (96x24x24, R=4,
+    same Re and Ma, inflow ramp, oscillating sphere) against the oracle:
+    velocity field and drag/lift coefficients."""
+    cfg = W.sphere_channel(96, 24, 24, radius=4.0, amplitude=1.0, period=800.0, ramp=50)
+    say("case: scaled sphere channel 96x24x24 %s" % storage)
+    kind, p = cfg["body"]
+    s, d = pair(27, 96, 24, 24, cfg["nu"], storage=storage, body=(kind, p), faces=cfg["faces"],
+                u_in=cfg["u_in"], ramp_steps=cfg["ramp_steps"])
+    norm = 0.5 * cfg["U"] ** 2 * math.pi * 16.0
+    worst_c = 0.0
+    for k in (40, 40, 40):
+        s.step(k)
+        d.step(k)
+        t = d.time
+        c = p[0:3] + p[4:7] * math.sin(p[7] * t + p[8])
+        xq, nq, wq = W.sphere_quadrature(c, 4.0, subdiv=3)
+        Fg, _ = s.wall_force(xq, nq, wq)
+        Fo, _, st = d.wall_force(xq, nq, wq)
+        worst_c = max(worst_c, np.max(np.abs(Fg - Fo)) / norm)
+    _, ug, _ = s.moments()
+    _, uo, _ = d.moments()
+    eu = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    say("  t=%d velocity rel L2 %.3e, max |dC| %.3e (Cd oracle %.4f)" % (d.time, eu, worst_c,
+                                                                         Fo[0] / norm))
+    assert eu <= tol_u
+    assert worst_c <= tol_f
+
+
+def test_full_batch_64_channels_batched_equals_per_instance():
+    """The batched workload at full size (64 channels, 5.6M nodes, FP32): one
+    launch per kernel for all instances and one launch per instance agree
+    bitwise after 60 steps."""
+    from paper_1710_02375_amd import lbm
+
+    chans = W.flap_channels(count=64, seed=2375)
+    descs = [dict(Q=9, nx=c["nx"], ny=c["ny"], nz=1, nu=c["nu"], storage="f32", faces=c["faces"],
+                  u_in=c["u_in"], inlet_profile=1) for c in chans]
+    say("case: 64 flap channels, %d nodes" % sum(d["nx"] * d["ny"] for d in descs))
+    outs = []
+    for mode in (0, 1):
+        s = lbm.Solver(descs)
+        for k, (c, dsc) in enumerate(zip(chans, descs)):
+            N = dsc["nx"] * dsc["ny"]
+            s.init_fields(np.ones(N), np.zeros((2, N)), inst=k)
+            s.set_body(*c["body"], inst=k)
+        s.set_launch_mode(mode)
+        s.step(60)
+        outs.append([s.get_populations(k) for k in (0, 17, 40, 63)])
+        _, _, tot = s.moments(inst=40)
+        assert tot["status"] == lbm.LBM_OK
+        s.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
