@@ -317,7 +317,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--variant", default=None, help="bulk-kernel variant (default: autotune)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64"])
-    ap.add_argument("--workload", default="tg256", choices=["tg256", "tg512", "sphere"],
+    ap.add_argument("--workload", default="tg256", choices=["tg256", "tg512", "sphere", "batched"],
                     help="tg256 is the headline line; the others print their own line")
     ap.add_argument("--sphere-steps", type=int, default=2000)
     ap.add_argument("--sphere-sample", type=int, default=100)
@@ -337,6 +337,13 @@ def main():
 
     if args.workload == "sphere":
         print(json.dumps(sphere_workload(lbm, torch, args)), flush=True)
+        return
+    if args.workload == "batched":
+        r = batched_form(lbm, torch, args.batched_steps, args.batched_warmup)
+        print(json.dumps({"metric": "aggregate MLUPS, batched vs per-instance launches",
+                          "unit": "MLUPS", "config": {"workload": "64 D2Q9 KBC flap channels "
+                                                      "(seed 2375), FP32"}, "forms": r}),
+              flush=True)
         return
     if args.workload == "tg512":
         print(json.dumps(tg512_workload(lbm, torch, args)), flush=True)

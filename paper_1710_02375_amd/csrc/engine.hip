@@ -391,7 +391,8 @@ lbm_status ensure_graph(lbm_ctx* c, int parity) {
 
 lbm_status check_error_word(lbm_ctx* c) {
   uint32_t v = 0;
-  HIPCHECK(c, hipMemcpy(&v, c->derr, sizeof v, hipMemcpyDeviceToHost));
+  HIPCHECK(c, hipMemcpyAsync(&v, c->derr, sizeof v, hipMemcpyDeviceToHost, c->stream));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
   if (v) return fail(c, LBM_ERR_NONFINITE, "a node reached an invalid state (rho <= 0, |u| >= 1 or non-finite)");
   return LBM_OK;
 }
@@ -658,12 +659,16 @@ lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_
     fail(c, LBM_ERR_DEVICE, "hipMemsetAsync failed");
     return bail(LBM_ERR_DEVICE);
   }
-  // Static flags of non-periodic face planes.
+  // Static flags of non-periodic face planes (uploaded on the context's
+  // stream, after the clears above; the host copies live until the final
+  // synchronisation).
+  std::vector<std::vector<uint8_t>> hflags(n_instances);
   for (int k = 0; k < n_instances; ++k) {
     const InstDev& I = c->hinst[k];
     if (I.flag_off < 0) continue;
     const lbm_instance_desc& d = desc[k];
-    std::vector<uint8_t> h((size_t)I.N, 0);
+    std::vector<uint8_t>& h = hflags[k];
+    h.assign((size_t)I.N, 0);
     for (int z = 0; z < d.nz; ++z)
       for (int y = 0; y < d.ny; ++y)
         for (int x = 0; x < d.nx; ++x) {
@@ -675,7 +680,8 @@ lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_
           }
           if (on) h[(size_t)x + (size_t)d.nx * ((size_t)y + (size_t)d.ny * z)] = FLAG_STATIC;
         }
-    if (hipMemcpy(c->flags + I.flag_off, h.data(), h.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpyAsync(c->flags + I.flag_off, h.data(), h.size(), hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess) {
       fail(c, LBM_ERR_DEVICE, "flag upload failed");
       return bail(LBM_ERR_DEVICE);
     }
@@ -755,7 +761,7 @@ lbm_status lbm_set_geometry(lbm_ctx* c, int inst, const lbm_body* body) {
   c->moving[inst] = (b.kind == LBM_BODY_SPHERE && p[7] != 0.0 && (p[4] != 0.0 || p[5] != 0.0 || p[6] != 0.0)) ||
                     (b.kind == LBM_BODY_FLAP && p[4] != 0.0 && p[3] != 0.0);
   if ((st = upload(c, &c->dinst, c->hinst))) return st;
-  HIPCHECK(c, hipMemcpy(c->dclock, &c->step, sizeof(int64_t), hipMemcpyHostToDevice));
+  HIPCHECK(c, hipMemcpyAsync(c->dclock, &c->step, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
   if ((st = full_geometry(c, inst))) return st;
   if ((st = rebuild_work(c))) return st;
   c->force_valid[inst] = 0;

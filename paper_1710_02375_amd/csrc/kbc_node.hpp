@@ -488,18 +488,31 @@ __device__ __forceinline__ bool collide(R (&d)[Q], const CollideParams<R>& P, Co
         }
       }
     const R dd = ss + R(2) * a + b;   // <Delta|Delta>
-    const bool near_eq = sizeof(R) == 4 && dd < R(P.near_eq);
+    // FP32 cannot resolve gamma when <Delta|Delta> is small or when <Dh|Dh>
+    // is below the normal range (its products may underflow to zero while
+    // <Dh|Dh> stays positive, and the reciprocal overflows): those nodes take
+    // gamma from FP64.  An exact equilibrium (Delta = 0) needs none: Dh = 0
+    // there and gamma does not enter the update.
+    bool near_eq = sizeof(R) == 4 && (dd < R(P.near_eq) || b < R(1e-30));
+    if (near_eq) {
+      bool zero = true;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) zero = zero && dl[i] == R(0);
+      near_eq = !zero;
+    }
     if (near_eq && DEFER) {
       out.fp64 = 1;
-      if (b > R(0)) gamma = P.inv_beta - (R(2) - P.inv_beta) * a * frcp(b);
+      if (b > R(1e-30)) gamma = P.inv_beta - (R(2) - P.inv_beta) * a * frcp(b);
     } else if (near_eq) {
       float tmp[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) tmp[i] = (float)d[i];
       gamma = (R)gamma_fp64<Q>(tmp, P.beta_d, P.trace_in_s);
       out.fp64 = 1;
-    } else if (b > R(0)) {
-      gamma = P.inv_beta - (R(2) - P.inv_beta) * a * frcp(b);
+    } else if (b > R(sizeof(R) == 8 ? 1e-300 : 1e-30)) {
+      // Below that <Dh|Dh> the reciprocal would overflow; Dh is then
+      // negligible and gamma = 2 is kept.
+      gamma = P.inv_beta - (R(2) - P.inv_beta) * (sizeof(R) == 8 ? a / b : a * frcp(b));
     }
   }
   // ---- post-collision state (Eqs. 1, 3): f - beta (2 Ds + gamma Dh) --------
