@@ -21,7 +21,7 @@
 using namespace kbc;
 
 // Workgroups of the FP64 pass over deferred near-equilibrium nodes.
-static constexpr int kFixupBlocks = 512;
+static constexpr int kFixupBlocks = 128;
 
 struct lbm_ctx {
   int device = 0;
@@ -51,7 +51,9 @@ struct lbm_ctx {
   int64_t* dclock = nullptr;
   uint32_t* derr = nullptr;
   uint32_t* herr = nullptr;       // pinned mirror of the error word
-  uint32_t* dneq_count = nullptr; // deferred near-equilibrium nodes of a step
+  uint32_t* dneq_count = nullptr; // two counters of deferred near-equilibrium nodes:
+                                  // a step with source buffer k appends to [k]
+  int last_src = -1;              // source buffer of the last step enqueued
   uint2* dneq_list = nullptr;
   hipEvent_t err_event = nullptr;
   bool err_pending = false;
@@ -336,7 +338,9 @@ lbm_status enqueue_step(lbm_ctx* c, int src) {
   b.err = c->derr;
   b.clock = c->dclock;
   b.stats = c->stats_enabled ? c->dstats : nullptr;
-  b.neq_count = c->dneq_count;
+  b.neq_count = c->dneq_count + src;
+  b.neq_next = c->dneq_count + (1 - src);
+  b.clock_tick = c->time_dependent ? c->dclock : nullptr;
   b.neq_list = c->dneq_list;
   b.neq_cap = (uint32_t)c->total_nodes;
   const int ngt = (int)c->gtiles.size();
@@ -358,7 +362,6 @@ lbm_status enqueue_step(lbm_ctx* c, int src) {
     }
   }
   HIPCHECK(c, c->ops->fixup(b, kFixupBlocks, ntiles + nbt, c->stream));
-  HIPCHECK(c, launch_step_end(c->dclock, c->dneq_count, c->time_dependent ? 1 : 0, c->stream));
   return LBM_OK;
 }
 
@@ -638,7 +641,7 @@ lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_
   if ((st = dev_alloc(c, foff, (void**)&c->flags))) return bail(st);
   if ((st = dev_alloc(c, sizeof(int64_t), (void**)&c->dclock))) return bail(st);
   if ((st = dev_alloc(c, sizeof(uint32_t), (void**)&c->derr))) return bail(st);
-  if ((st = dev_alloc(c, sizeof(uint32_t), (void**)&c->dneq_count))) return bail(st);
+  if ((st = dev_alloc(c, 2 * sizeof(uint32_t), (void**)&c->dneq_count))) return bail(st);
   if ((st = dev_alloc(c, (size_t)c->total_nodes * sizeof(uint2), (void**)&c->dneq_list))) return bail(st);
   if (hipHostMalloc((void**)&c->herr, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
     fail(c, LBM_ERR_OOM, "hipHostMalloc failed");
@@ -655,7 +658,7 @@ lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_
       hipMemsetAsync(c->flags, 0, foff, c->stream) != hipSuccess ||
       hipMemsetAsync(c->dclock, 0, sizeof(int64_t), c->stream) != hipSuccess ||
       hipMemsetAsync(c->derr, 0, sizeof(uint32_t), c->stream) != hipSuccess ||
-      hipMemsetAsync(c->dneq_count, 0, sizeof(uint32_t), c->stream) != hipSuccess) {
+      hipMemsetAsync(c->dneq_count, 0, 2 * sizeof(uint32_t), c->stream) != hipSuccess) {
     fail(c, LBM_ERR_DEVICE, "hipMemsetAsync failed");
     return bail(LBM_ERR_DEVICE);
   }
@@ -777,17 +780,24 @@ lbm_status lbm_step(lbm_ctx* c, int n_steps) {
   }
   lbm_status st;
   int n = n_steps;
+  // A step with source buffer k appends to counter k, which the previous
+  // step (source 1 - k) cleared.  If the source did not alternate (state
+  // restored by the host), clear both here, outside any captured graph.
+  if (n > 0 && c->last_src == c->cur)
+    HIPCHECK(c, hipMemsetAsync(c->dneq_count, 0, 2 * sizeof(uint32_t), c->stream));
   while (n > 0) {
     if (c->use_graph && n >= 2 && !c->graph_failed) {
       if ((st = ensure_graph(c, c->cur))) return st;
       if (c->graph[c->cur]) {
         HIPCHECK(c, hipGraphLaunch(c->graph[c->cur], c->stream));
+        c->last_src = 1 - c->cur;
         n -= 2;
         c->step += 2;
         continue;
       }
     }
     if ((st = enqueue_step(c, c->cur))) return st;
+    c->last_src = c->cur;
     c->cur ^= 1;
     c->step += 1;
     n -= 1;

@@ -491,15 +491,12 @@ __device__ __forceinline__ bool collide(R (&d)[Q], const CollideParams<R>& P, Co
     // FP32 cannot resolve gamma when <Delta|Delta> is small or when <Dh|Dh>
     // is below the normal range (its products may underflow to zero while
     // <Dh|Dh> stays positive, and the reciprocal overflows): those nodes take
-    // gamma from FP64.  An exact equilibrium (Delta = 0) needs none: Dh = 0
-    // there and gamma does not enter the update.
-    bool near_eq = sizeof(R) == 4 && (dd < R(P.near_eq) || b < R(1e-30));
-    if (near_eq) {
-      bool zero = true;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) zero = zero && dl[i] == R(0);
-      near_eq = !zero;
-    }
+    // gamma from FP64.  Not when <Ds|Ds> and <Dh|Dh> are both zero (the rest
+    // state, or deviations so small that every product underflows): |gamma
+    // Dh| is then of the order of |Ds| + |Dh|, far below the population
+    // rounding.
+    const bool near_eq = sizeof(R) == 4 && (dd < R(P.near_eq) || b < R(1e-30)) &&
+                         (b > R(0) || ss > R(0));
     if (near_eq && DEFER) {
       out.fp64 = 1;
       if (b > R(1e-30)) gamma = P.inv_beta - (R(2) - P.inv_beta) * a * frcp(b);

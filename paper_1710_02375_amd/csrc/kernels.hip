@@ -660,6 +660,13 @@ __global__ void __launch_bounds__(256) k_neq_fixup(StepBuffers b, int stat0) {
   using S = Store<ST>;
   using T = typename S::T;
   using R = typename S::R;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // End of the step: the next step appends to the other counter, which no
+    // kernel of this step reads; only the geometry and boundary kernels,
+    // which ran before, read the clock.
+    *b.neq_next = 0u;
+    if (b.clock_tick) *b.clock_tick += 1;
+  }
   const uint32_t n = min(*b.neq_count, b.neq_cap);
   float gmin = 1e30f, gmax = -1e30f;
   double gsum = 0.0;
@@ -697,12 +704,6 @@ __global__ void __launch_bounds__(256) k_neq_fixup(StepBuffers b, int stat0) {
   if (b.stats) block_stats<256>(gmin, gmax, gsum, cnt, f64, b.stats + stat0 + blockIdx.x);
 }
 
-__global__ void k_step_end(int64_t* clock, uint32_t* neq_count, int tick) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    *neq_count = 0u;
-    if (tick) clock[0] += 1;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Initialisation, checkpoint encode/decode, moments.
@@ -935,7 +936,7 @@ __global__ void __launch_bounds__(256) k_force(const InstDev* __restrict__ insts
 }
 
 // ---------------------------------------------------------------------------
-// Clock and reductions
+// Reductions
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_reduce(const double* partials, int n, int width,
                                                 double* out) {
@@ -1135,11 +1136,6 @@ const Ops* get_ops(int Q, int storage) {
     }
   }
   return nullptr;
-}
-
-hipError_t launch_step_end(int64_t* clock, uint32_t* neq_count, int tick, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, s, clock, neq_count, tick);
-  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const double* partials, int n, int width, double* out, hipStream_t s) {

@@ -33,6 +33,8 @@ struct StepBuffers {
   uint32_t* neq_count;    // near-equilibrium nodes deferred to the FP64 pass
   uint2* neq_list;        // (instance, node) of each deferred node
   uint32_t neq_cap;
+  uint32_t* neq_next;     // the next step's counter, cleared by the FP64 pass
+  int64_t* clock_tick;    // advanced by one at the end of the step, or null
 };
 
 struct Ops {
@@ -66,7 +68,8 @@ struct Ops {
                         int* nparts, hipStream_t s);
   // Redoes the deferred near-equilibrium nodes with the FP64 gamma (grid of
   // nblocks workgroups striding over the list); statistics go to
-  // stats[stat0 + workgroup].
+  // stats[stat0 + workgroup].  It also ends the step: clears neq_next and
+  // advances clock_tick.
   hipError_t (*fixup)(const StepBuffers& b, int nblocks, int stat0, hipStream_t s);
   // Wall force (per point traction, per-workgroup partial force sums).
   hipError_t (*force)(const InstDev* insts, int inst, const void* prev, const uint8_t* flags,
@@ -85,9 +88,6 @@ int bulk_variant_tile(int v);
 // base per instance (requires Q * stride * sizeof(storage) < 2^32).
 bool bulk_variant_off32(int v);
 
-// End of a step: clears the deferred-node count and, if tick, advances the
-// device clock.
-hipError_t launch_step_end(int64_t* clock, uint32_t* neq_count, int tick, hipStream_t s);
 // Sums `width` doubles over n partials in a fixed order into out[width].
 hipError_t launch_reduce(const double* partials, int n, int width, double* out, hipStream_t s);
 hipError_t launch_reduce_stats(const StatPartial* parts, int n, StatPartial* out, hipStream_t s);

@@ -145,8 +145,12 @@ enum : uint8_t {
 };
 
 // Default threshold on <Delta|Delta> below which the FP32 paths take gamma
-// from FP64.
-constexpr float kNearEq = 1e-10f;
+// from FP64.  At <Delta|Delta> = 1e-12 the entries of Delta are ~1e-6
+// sqrt(W_i / Q) and their FP32 rounding (~1e-9) perturbs gamma by a few
+// percent; gamma Dh then moves by about the FP32 rounding of the populations.
+// (D3Q27 Taylor-Green 32^3, Re 1600, 1000 steps: FP32 velocity error against
+// FP64 2.9e-6 with this threshold, 3.2e-6 with 1e-10.)
+constexpr float kNearEq = 1e-12f;
 
 // Per-instance descriptor read by every kernel (device memory, one per
 // instance).  Populations of the instance live at buf + pop_off + i*stride.
