@@ -334,6 +334,9 @@ __device__ __forceinline__ bool collide(R (&d)[Q], const CollideParams<R>& P, Co
   }
   const R rho = R(1) + rt;
   const R ir = frcp(rho);
+  // Size of the terms that cancel in Delta = d - (f^eq - W): FP32 keeps
+  // Delta to ~6e-8 of sqrt(dscale) in the 1/W-weighted norm.
+  const R dscale = rt * rt + R(3) * (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]);
   const R u[3] = {j[0] * ir, j[1] * ir, j[2] * ir};
   const bool ok = rho > R(0) && u[0] < R(1) && u[0] > R(-1) && u[1] < R(1) && u[1] > R(-1) &&
                   u[2] < R(1) && u[2] > R(-1);
@@ -488,25 +491,25 @@ __device__ __forceinline__ bool collide(R (&d)[Q], const CollideParams<R>& P, Co
         }
       }
     const R dd = ss + R(2) * a + b;   // <Delta|Delta>
-    // FP32 cannot resolve gamma when <Delta|Delta> is small or when <Dh|Dh>
-    // is below the normal range (its products may underflow to zero while
-    // <Dh|Dh> stays positive, and the reciprocal overflows): those nodes take
-    // gamma from FP64.  Not when <Ds|Ds> and <Dh|Dh> are both zero (the rest
-    // state, or deviations so small that every product underflows): |gamma
-    // Dh| is then of the order of |Ds| + |Dh|, far below the population
-    // rounding.
-    const bool near_eq = sizeof(R) == 4 && (dd < R(P.near_eq) || b < R(1e-30)) &&
+    // FP32 cannot resolve gamma when <Delta|Delta> is small against the
+    // terms that cancelled in Delta (relative threshold near_eq on dscale),
+    // or when <Dh|Dh> nears the bottom of the normal range (products
+    // underflow, the reciprocal overflows): those nodes take gamma from FP64.
+    // Not when <Ds|Ds> and <Dh|Dh> are both zero (the rest state, or
+    // deviations so small that every product underflows): |gamma Dh| is then
+    // of the order of |Ds| + |Dh|, far below the population rounding.
+    const bool near_eq = sizeof(R) == 4 && (dd < R(P.near_eq) * dscale || b < R(1e-36)) &&
                          (b > R(0) || ss > R(0));
     if (near_eq && DEFER) {
       out.fp64 = 1;
-      if (b > R(1e-30)) gamma = P.inv_beta - (R(2) - P.inv_beta) * a * frcp(b);
+      if (b > R(1e-36)) gamma = P.inv_beta - (R(2) - P.inv_beta) * a * frcp(b);
     } else if (near_eq) {
       float tmp[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) tmp[i] = (float)d[i];
       gamma = (R)gamma_fp64<Q>(tmp, P.beta_d, P.trace_in_s);
       out.fp64 = 1;
-    } else if (b > R(sizeof(R) == 8 ? 1e-300 : 1e-30)) {
+    } else if (b > R(sizeof(R) == 8 ? 1e-300 : 1e-36)) {
       // Below that <Dh|Dh> the reciprocal would overflow; Dh is then
       // negligible and gamma = 2 is kept.
       gamma = P.inv_beta - (R(2) - P.inv_beta) * (sizeof(R) == 8 ? a / b : a * frcp(b));

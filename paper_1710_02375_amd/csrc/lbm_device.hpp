@@ -144,13 +144,13 @@ enum : uint8_t {
   FLAG_SPECIAL = FLAG_SOLID | FLAG_STATIC | FLAG_BODY,
 };
 
-// Default threshold on <Delta|Delta> below which the FP32 paths take gamma
-// from FP64.  At <Delta|Delta> = 1e-12 the entries of Delta are ~1e-6
-// sqrt(W_i / Q) and their FP32 rounding (~1e-9) perturbs gamma by a few
-// percent; gamma Dh then moves by about the FP32 rounding of the populations.
-// (D3Q27 Taylor-Green 32^3, Re 1600, 1000 steps: FP32 velocity error against
-// FP64 2.9e-6 with this threshold, 3.2e-6 with 1e-10.)
-constexpr float kNearEq = 1e-12f;
+// Default relative threshold: FP32 paths take gamma from FP64 where
+// <Delta|Delta> < kNearEq * (rt^2 + 3 |j|^2), the squared size of the terms
+// that cancel in Delta.  FP32 keeps Delta to ~6e-8 of that size, so at the
+// threshold gamma is perturbed by ~0.6%, which moves gamma Dh by about the
+// FP32 rounding of the populations.  A near-rest node (small rt and j) keeps
+// its relative precision and needs no FP64 however small Delta is.
+constexpr float kNearEq = 1e-10f;
 
 // Per-instance descriptor read by every kernel (device memory, one per
 // instance).  Populations of the instance live at buf + pop_off + i*stride.
@@ -163,7 +163,7 @@ struct InstDev {
   FastDiv divx, divy;
   double beta;
   float beta_f;
-  float near_eq;      // <Delta|Delta> below which FP32 paths take gamma from FP64
+  float near_eq;      // relative <Delta|Delta> threshold for the FP64 gamma
   int collision;
   int trace_in_s;
   int inlet_profile;

@@ -224,7 +224,12 @@ def test_geometry_errors():
     assert ei.value.status == lbm.LBM_ERR_INVALID   # no step since set-up
 
 
-@pytest.mark.parametrize("storage,tol_f,tol_u", [("f64", 1e-12, 1e-12), ("f32", 5e-6, 1e-5),
+# Force-coefficient tolerances.  FP32: rounding leaves ~1e-8 per node in the
+# stress rho/3 + rho nu S that the force integrates (Sec. II.C.2); a uniform
+# offset cancels over the closed surface, and the rest, over 4 pi R^2 and
+# normalised by U^2 pi R^2 / 2, is ~1e-5.  FP16: the same with the 2^-11
+# storage rounding of the deviations.
+@pytest.mark.parametrize("storage,tol_f,tol_u", [("f64", 1e-12, 1e-12), ("f32", 2e-5, 1e-5),
                                                   ("f16", 5e-2, 5e-3)])
 def test_sphere_channel_scaled_parity(storage, tol_f, tol_u):
     """The sphere-channel workload at a quarter of its size (96x24x24, R=4,
