@@ -22,6 +22,8 @@ using namespace kbc;
 
 // Workgroups of the FP64 pass over deferred near-equilibrium nodes.
 static constexpr int kFixupBlocks = 128;
+// Upper bound on the one-wavefront workgroups of a boundary launch.
+static constexpr int kBoundaryWorkgroups = 4096;
 
 struct lbm_ctx {
   int device = 0;
@@ -55,6 +57,19 @@ struct lbm_ctx {
                                   // a step with source buffer k appends to [k]
   int last_src = -1;              // source buffer of the last step enqueued
   uint2* dneq_list = nullptr;
+  // Boundary node lists (two per launch: nodes with missing populations,
+  // then inflow / outflow plane nodes): instance k's pair starts at
+  // 2 bl_off[k] (capacity bl_cap[k] each, its box-tile volume); the batched
+  // launch uses the whole allocation with capacity bl_total.  Counter pairs:
+  // [2k, 2k+1] per instance, [2 n_inst, 2 n_inst + 1] batched.
+  uint2* dblist = nullptr;
+  size_t dblist_cap = 0;
+  uint32_t* dbcount = nullptr;
+  std::vector<uint32_t> bl_off, bl_cap;
+  uint32_t bl_total = 0;
+  int bl_nwg_all = 0, bl_nfb_all = 0; // workgroups of the batched boundary launch
+  std::vector<int> bl_nwg, bl_nfb, bl_stat;   // per instance, and stats offsets
+  int bstat_slots = 0;                // stats slots reserved for boundary launches
   hipEvent_t err_event = nullptr;
   bool err_pending = false;
   int64_t step = 0;
@@ -236,7 +251,7 @@ void push_box_tiles(std::vector<BoxTile>& out, int region, const Region& r) {
 
 // Statistics slots: bulk tiles, boundary tiles, then the FP64-pass workgroups.
 lbm_status ensure_stats(lbm_ctx* c) {
-  const size_t need = c->tiles.size() + c->btiles.size() + kFixupBlocks + 1;
+  const size_t need = c->tiles.size() + (size_t)c->bstat_slots + kFixupBlocks + 1;
   if (need <= c->dstats_cap) return LBM_OK;
   dev_free(c, c->dstats);
   c->dstats = nullptr;
@@ -295,6 +310,46 @@ lbm_status rebuild_work(lbm_ctx* c) {
     if (c->moving[k] && geom_region[k] >= 0)
       push_box_tiles(c->gtiles, geom_region[k], c->regions[geom_region[k]]);
   }
+  // Boundary node lists and their launch shapes.
+  {
+    const int ng = boundary_nodes_per_workgroup(c->Q);
+    auto nwg_for = [&](uint32_t cap) {
+      return (int)std::min<uint64_t>(kBoundaryWorkgroups, (cap + ng - 1) / ng);
+    };
+    auto nfb_for = [&](uint32_t cap) {
+      return (int)std::min<uint64_t>(kBoundaryWorkgroups / 4, (cap + 255) / 256);
+    };
+    c->bl_off.assign(c->n_inst, 0);
+    c->bl_cap.assign(c->n_inst, 0);
+    c->bl_nwg.assign(c->n_inst, 0);
+    c->bl_nfb.assign(c->n_inst, 0);
+    c->bl_stat.assign(c->n_inst, 0);
+    uint32_t off = 0;
+    int sum_nwg = 0;
+    for (int k = 0; k < c->n_inst; ++k) {
+      uint32_t cap = 0;
+      for (int t = c->bt_first[k]; t < c->bt_first[k] + c->bt_count[k]; ++t) cap += c->btiles[t].count;
+      c->bl_off[k] = off;
+      c->bl_cap[k] = cap;
+      c->bl_nwg[k] = nwg_for(cap);
+      c->bl_nfb[k] = nfb_for(cap);
+      c->bl_stat[k] = sum_nwg;
+      sum_nwg += c->bl_nwg[k] + c->bl_nfb[k];
+      off += cap;
+    }
+    c->bl_total = off;
+    c->bl_nwg_all = nwg_for(off);
+    c->bl_nfb_all = nfb_for(off);
+    c->bstat_slots = std::max(c->bl_nwg_all + c->bl_nfb_all, sum_nwg);
+    if ((size_t)off > c->dblist_cap) {
+      dev_free(c, c->dblist);
+      c->dblist = nullptr;
+      c->dblist_cap = 0;
+      lbm_status st2 = dev_alloc(c, 2 * (size_t)off * sizeof(uint2), (void**)&c->dblist);
+      if (st2) return st2;
+      c->dblist_cap = off;
+    }
+  }
   lbm_status st;
   if ((st = upload(c, &c->dregions, c->regions))) return st;
   if ((st = upload(c, &c->dbtiles, c->btiles))) return st;
@@ -341,6 +396,8 @@ lbm_status enqueue_step(lbm_ctx* c, int src) {
   b.neq_count = c->dneq_count + src;
   b.neq_next = c->dneq_count + (1 - src);
   b.clock_tick = c->time_dependent ? c->dclock : nullptr;
+  b.bcount = c->dbcount;
+  b.nbcount = 2 * (c->n_inst + 1);
   b.neq_list = c->dneq_list;
   b.neq_cap = (uint32_t)c->total_nodes;
   const int ngt = (int)c->gtiles.size();
@@ -351,17 +408,21 @@ lbm_status enqueue_step(lbm_ctx* c, int src) {
   const int ntiles = (int)c->tiles.size();
   const int nbt = (int)c->btiles.size();
   if (c->launch_mode == 0) {
-    HIPCHECK(c, c->ops->boundary(b, c->dregions, c->dbtiles, 0, nbt, ntiles, c->stream));
+    HIPCHECK(c, c->ops->boundary(b, c->dregions, c->dbtiles, 0, nbt, c->dblist, c->bl_total,
+                                 c->dbcount + 2 * c->n_inst, c->bl_nwg_all, c->bl_nfb_all, ntiles,
+                                 c->stream));
     HIPCHECK(c, c->ops->bulk(c->variant, b, c->dtiles, 0, ntiles, c->stream));
   } else {
     for (int k = 0; k < c->n_inst; ++k) {
       HIPCHECK(c, c->ops->boundary(b, c->dregions, c->dbtiles, c->bt_first[k], c->bt_count[k],
-                                   ntiles + c->bt_first[k], c->stream));
+                                   c->dblist + 2 * (size_t)c->bl_off[k], c->bl_cap[k],
+                                   c->dbcount + 2 * k, c->bl_nwg[k], c->bl_nfb[k],
+                                   ntiles + c->bl_stat[k], c->stream));
       HIPCHECK(c, c->ops->bulk(c->variant, b, c->dtiles, c->tile_first[k], c->tile_count[k],
                                c->stream));
     }
   }
-  HIPCHECK(c, c->ops->fixup(b, kFixupBlocks, ntiles + nbt, c->stream));
+  HIPCHECK(c, c->ops->fixup(b, kFixupBlocks, ntiles + c->bstat_slots, c->stream));
   return LBM_OK;
 }
 
@@ -514,6 +575,8 @@ lbm_status lbm_destroy(lbm_ctx* c) {
   dev_free(c, c->derr);
   dev_free(c, c->dneq_count);
   dev_free(c, c->dneq_list);
+  dev_free(c, c->dblist);
+  dev_free(c, c->dbcount);
   dev_free(c, c->dtiles);
   dev_free(c, c->dregions);
   dev_free(c, c->dbtiles);
@@ -643,6 +706,7 @@ lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_
   if ((st = dev_alloc(c, sizeof(uint32_t), (void**)&c->derr))) return bail(st);
   if ((st = dev_alloc(c, 2 * sizeof(uint32_t), (void**)&c->dneq_count))) return bail(st);
   if ((st = dev_alloc(c, (size_t)c->total_nodes * sizeof(uint2), (void**)&c->dneq_list))) return bail(st);
+  if ((st = dev_alloc(c, 2 * (size_t)(n_instances + 1) * sizeof(uint32_t), (void**)&c->dbcount))) return bail(st);
   if (hipHostMalloc((void**)&c->herr, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
     fail(c, LBM_ERR_OOM, "hipHostMalloc failed");
     return bail(LBM_ERR_OOM);
@@ -658,7 +722,8 @@ lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_
       hipMemsetAsync(c->flags, 0, foff, c->stream) != hipSuccess ||
       hipMemsetAsync(c->dclock, 0, sizeof(int64_t), c->stream) != hipSuccess ||
       hipMemsetAsync(c->derr, 0, sizeof(uint32_t), c->stream) != hipSuccess ||
-      hipMemsetAsync(c->dneq_count, 0, 2 * sizeof(uint32_t), c->stream) != hipSuccess) {
+      hipMemsetAsync(c->dneq_count, 0, 2 * sizeof(uint32_t), c->stream) != hipSuccess ||
+      hipMemsetAsync(c->dbcount, 0, 2 * (size_t)(n_instances + 1) * sizeof(uint32_t), c->stream) != hipSuccess) {
     fail(c, LBM_ERR_DEVICE, "hipMemsetAsync failed");
     return bail(LBM_ERR_DEVICE);
   }
@@ -842,12 +907,13 @@ lbm_status lbm_moments(lbm_ctx* c, int inst, double* rho, double* u, lbm_totals*
   if (e == hipSuccess && tot && c->stats_enabled && c->step > 0) {
     StatPartial* so = reinterpret_cast<StatPartial*>(dout + 8);
     e = launch_reduce_stats(c->dstats + c->tile_first[inst], c->tile_count[inst], so, c->stream);
+    // The boundary and FP64 passes serve all instances at once; their nodes
+    // are attributed to the instance only in single-instance contexts.
     if (e == hipSuccess)
-      e = launch_reduce_stats(c->dstats + c->tiles.size() + c->bt_first[inst], c->bt_count[inst], so + 1, c->stream);
-    // The FP64 pass serves all instances at once; its nodes are attributed
-    // to the instance only in single-instance contexts.
+      e = launch_reduce_stats(c->dstats + c->tiles.size(), c->n_inst == 1 ? c->bstat_slots : 0,
+                              so + 1, c->stream);
     if (e == hipSuccess)
-      e = launch_reduce_stats(c->dstats + c->tiles.size() + c->btiles.size(),
+      e = launch_reduce_stats(c->dstats + c->tiles.size() + c->bstat_slots,
                               c->n_inst == 1 ? kFixupBlocks : 0, so + 2, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sp, so, sizeof sp, hipMemcpyDeviceToHost, c->stream);
     have_stats = true;

@@ -532,54 +532,471 @@ __device__ __forceinline__ bool in_region(const Region& rg, int x, int y, int z)
          z < rg.hi[2];
 }
 
-template <int Q, int ST>
-__global__ void __launch_bounds__(256) k_boundary(StepBuffers b, const Region* __restrict__ regions,
-                                                  const BoxTile* __restrict__ btiles, int bt0,
-                                                  int stat0) {
-  using S = Store<ST>;
-  using T = typename S::T;
-  using R = typename S::R;
+// Boundary node lists: the special nodes (face planes, cut links) of the
+// scanned regions, each once (a node inside an earlier region of its instance
+// belongs to that region's tiles), as (instance, node) pairs appended with one
+// atomic per wave.  Nodes on an inflow or outflow plane go to list[cap + ...]
+// (count[1]); the others, whose missing populations Grad's approximation
+// fills, to list[...] (count[0]).
+template <int Q>
+__global__ void __launch_bounds__(256) k_boundary_scan(const InstDev* __restrict__ insts,
+                                                       const Region* __restrict__ regions,
+                                                       const BoxTile* __restrict__ btiles, int bt0,
+                                                       const uint8_t* __restrict__ flags,
+                                                       uint2* list, uint32_t cap, uint32_t* count) {
   const BoxTile bt = btiles[bt0 + blockIdx.x];
   const Region rg = regions[bt.region];
-  const InstDev& I = b.insts[rg.inst];
-  const T* sb = static_cast<const T*>(b.src) + I.pop_off;
-  T* db = static_cast<T*>(b.dst) + I.pop_off;
-  const uint8_t* fl = I.flag_off >= 0 ? b.flags + I.flag_off : nullptr;
-  const double t1 = (double)(*b.clock + 1);
-  CollideParams<R> P;
-  P.beta = (R)I.beta;
-  P.inv_beta = (R)(1.0 / I.beta);
-  P.beta_d = I.beta;
-  P.lbgk = I.collision;
-  P.trace_in_s = I.trace_in_s;
-  P.near_eq = I.near_eq;
-  float gmin = 1e30f, gmax = -1e30f;
-  double gsum = 0.0;
-  uint32_t cnt = 0, f64 = 0;
-  for (int k = threadIdx.x; k < bt.count; k += 256) {
-    int x, y, z;
-    if (!box_local(rg, bt.local0 + k, x, y, z)) continue;
+  const InstDev& I = insts[rg.inst];
+  const int k = threadIdx.x;
+  bool take = false, face = false;
+  uint32_t node = 0;
+  int x, y, z;
+  if (k < bt.count && I.flag_off >= 0 && box_local(rg, bt.local0 + k, x, y, z)) {
     bool owned = true;
     for (int r = rg.first; r < bt.region; ++r)
       if (in_region(regions[r], x, y, z)) owned = false;
-    if (!owned) continue;
-    const uint32_t node = node_index(I, x, y, z);
-    if (!fl) continue;
-    const uint8_t fv = fl[node];
-    if ((fv & FLAG_SOLID) || !(fv & (FLAG_STATIC | FLAG_BODY))) continue;
-    R f[Q];
-    gather_pre<Q, ST>(I, sb, fl, x, y, z, t1, f);
-    CollideOut co;
-    if (!collide<Q, R>(f, P, co)) atomicOr(b.err, 1u);
+    node = node_index(I, x, y, z);
+    const uint8_t fv = flags[I.flag_off + node];
+    take = owned && !(fv & FLAG_SOLID) && (fv & (FLAG_STATIC | FLAG_BODY));
+    face = (x == 0 && I.face[0] == LBM_FACE_INLET) || (x == I.nx - 1 && I.face[1] == LBM_FACE_OUTLET);
+  }
+  const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) db[i * I.stride + node] = S::enc(f[i]);
+  for (int which = 0; which < 2; ++which) {
+    const bool mine = take && (face == (which == 1));
+    const uint64_t m = __ballot(mine);
+    if (m) {
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(count + which, (uint32_t)__popcll(m));
+      base = __shfl(base, leader);
+      if (mine) {
+        const uint32_t slot = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        if (slot < cap) list[which * cap + slot] = make_uint2((uint32_t)rg.inst, node);
+      }
+    }
+  }
+}
+
+// Inflow / outflow plane nodes, one thread per node (Sec. III.A.1 inflow
+// with its ramp): equilibrium at the inflow velocity and the lagged density of
+// x + e_x, or at density 1 and the lagged velocity of x - e_x; then the
+// collision in FP64 like every boundary node.
+template <int Q, int ST>
+__global__ void __launch_bounds__(256) k_boundary_face(StepBuffers b, const uint2* __restrict__ list,
+                                                      const uint32_t* __restrict__ count,
+                                                      uint32_t cap, int stat0) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  const double t1 = (double)(*b.clock + 1);
+  float gmin = 1e30f, gmax = -1e30f;
+  double gsum = 0.0;
+  uint32_t cnt = 0, f64 = 0;
+  const uint32_t n = min(*count, cap);
+  for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+    const uint2 e = list[k];
+    const InstDev& I = b.insts[e.x];
+    const T* sb = static_cast<const T*>(b.src) + I.pop_off;
+    T* db = static_cast<T*>(b.dst) + I.pop_off;
+    const uint8_t* fl = b.flags + I.flag_off;
+    const Coord c = node_coord(I, e.y);
+    const bool inlet = c.x == 0 && I.face[0] == LBM_FACE_INLET;
+    double rt = 0.0, u[3] = {0.0, 0.0, 0.0};
+    uint32_t m;
+    if (resolve_nb(I, c.x, c.y, c.z, inlet ? 1 : -1, 0, 0, m) && !(fl[m] & FLAG_SOLID)) {
+      double r = 0.0, j3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        const double v = (double)S::dec(sb[p * I.stride + m]);
+        r += v;
+        if (cx(p) > 0) j3[0] += v;
+        if (cx(p) < 0) j3[0] -= v;
+        if (cy(p) > 0) j3[1] += v;
+        if (cy(p) < 0) j3[1] -= v;
+        if (cz<Q>(p) > 0) j3[2] += v;
+        if (cz<Q>(p) < 0) j3[2] -= v;
+      }
+      if (inlet) {
+        rt = r;
+      } else {
+        const double ir = 1.0 / (1.0 + r);
+        for (int a = 0; a < 3; ++a) u[a] = j3[a] * ir;
+      }
+    }
+    if (inlet) inflow_velocity(I, c.y, c.z, t1, u);
+    double f[Q];
+    feq_dev<Q, double>(rt, u, f);
+    CollideParams<double> P;
+    P.beta = I.beta;
+    P.inv_beta = 1.0 / I.beta;
+    P.beta_d = I.beta;
+    P.lbgk = I.collision;
+    P.trace_in_s = I.trace_in_s;
+    P.near_eq = I.near_eq;
+    CollideOut co;
+    if (!collide<Q, double>(f, P, co)) atomicOr(b.err, 1u);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) db[i * I.stride + e.y] = S::enc_d(f[i]);
     gmin = fminf(gmin, co.gamma);
     gmax = fmaxf(gmax, co.gamma);
     gsum += co.gamma;
     cnt += 1;
-    f64 += co.fp64;
+    f64 += 1;
   }
   if (b.stats) block_stats<256>(gmin, gmax, gsum, cnt, f64, b.stats + stat0 + blockIdx.x);
+}
+
+// Sum over the GL lanes of a group (GL a power of two <= 64), same value in
+// every lane of the group, fixed order.
+template <int GL>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = GL / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Value for lattice velocity component c in {0, +1, -1}; the operands are
+// plain values so that a per-lane choice stays a register select.
+__device__ __forceinline__ double pick3(int c, double v0, double vp, double vm) {
+  return c == 0 ? v0 : (c > 0 ? vp : vm);
+}
+
+// Lagged-field slot of x + k c_i (k = 1, 2), slot 0 being x itself.
+template <int Q>
+__device__ __forceinline__ int lag_slot(int i, int k) {
+  return 1 + 2 * (i < rest<Q>() ? i : i - 1) + (k - 1);
+}
+
+// ---------------------------------------------------------------------------
+// Nodes with missing populations (walls, cut links), one group of GL lanes
+// per node (GL = 64 for D3Q27, 32 for D2Q9: two nodes per wavefront).
+// gather_pre above does the same work in one thread, reading the lagged
+// moments of up to 2(Q-1)+1 neighbours one after another; here the lanes take
+// them in parallel:
+//   lane i < Q            source of population i (pull, wall, solid),
+//                         A_opp(i)(x), cut fraction and wall velocity;
+//   lane l < 2(Q-1)+1     lagged (rho~, u) of x (l = 0) or x + k c_i where
+//                         Grad's target velocity or the velocity gradient
+//                         needs it;
+//   lane 0 of the group   Grad target values (Sec. II.C.1);
+//   lane i < Q            f*_i for the missing i, then the KBC collision
+//                         (Eqs. 1-6) lane-parallel in FP64 with group sums,
+//                         and the store of population i.
+// The arithmetic of the boundary nodes is FP64 for every storage form.
+// Workgroups (one wavefront) stride over the node list.
+// ---------------------------------------------------------------------------
+template <int Q, int ST>
+__global__ void __launch_bounds__(64) k_boundary_wave(StepBuffers b, const uint2* __restrict__ list,
+                                                     const uint32_t* __restrict__ count,
+                                                     uint32_t cap, int stat0) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  constexpr int D = dims<Q>();
+  constexpr int GL = Q == 27 ? 64 : 32;
+  constexpr int NG = 64 / GL;                 // nodes per wavefront
+  constexpr int NS = 2 * (Q - 1) + 1;
+  static_assert(NS <= GL, "one lane per lagged-field slot");
+  __shared__ double s_f[NG][Q], s_opp[NG][Q], s_q[NG][Q], s_uw[NG][Q][3];
+  __shared__ double s_lr[NG][NS], s_lu[NG][NS][3];
+  __shared__ int s_lf[NG][NS];
+  __shared__ uint32_t s_miss[NG];
+  __shared__ double s_t[NG][10];   // rho_t, u_t[3], Pi[6]
+  const int g = threadIdx.x / GL, lane = threadIdx.x % GL;
+  const double t1 = (double)(*b.clock + 1);
+  float gmin = 1e30f, gmax = -1e30f;
+  double gsum = 0.0;
+  uint32_t cnt = 0, f64 = 0;
+  const uint32_t n = min(*count, cap);
+  for (uint32_t base = blockIdx.x * NG; base < n; base += gridDim.x * NG) {
+    const uint32_t k = base + g;
+    const bool active = k < n;
+    const uint2 e = active ? list[k] : make_uint2(0u, 0u);
+    const InstDev& I = b.insts[e.x];
+    const T* sb = static_cast<const T*>(b.src) + I.pop_off;
+    T* db = static_cast<T*>(b.dst) + I.pop_off;
+    const uint8_t* fl = b.flags + (I.flag_off >= 0 ? I.flag_off : 0);
+    const int64_t stride = I.stride;
+    const Coord c = node_coord(I, e.y);
+    const int x = c.x, y = c.y, z = c.z;
+    const uint32_t me = e.y;
+    if (lane == 0) s_miss[g] = 0u;
+    __syncthreads();
+    // ---- sources of the populations, cut links --------------------------
+    // (Nodes on inflow / outflow planes are on the other list: every source
+    // here is a node or a wall.)  The flag and the population are loaded
+    // together; a solid source's value is dropped.
+    if (active && lane < Q) {
+      const int i = lane;
+      int sr[3] = {x - cx(i), y - cy(i), z - cz<Q>(i)};
+      const int nn[3] = {I.nx, I.ny, I.nz};
+      bool w = false;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (sr[a] >= 0 && sr[a] < nn[a]) continue;
+        if (I.face[2 * a + (sr[a] < 0 ? 0 : 1)] == LBM_FACE_PERIODIC) sr[a] = (sr[a] + nn[a]) % nn[a];
+        else w = true;
+      }
+      double fi = 0.0;
+      bool missing = w;
+      const T opp = sb[(Q - 1 - i) * stride + me];
+      if (!w) {
+        const uint32_t m = node_index(I, sr[0], sr[1], sr[2]);
+        const uint8_t fs = fl[m];
+        const T v = sb[i * stride + m];
+        if (fs & FLAG_SOLID) missing = true;
+        else fi = (double)S::dec(v);
+      }
+      s_f[g][i] = fi;
+      if (missing) {
+        atomicOr(&s_miss[g], 1u << i);
+        s_opp[g][i] = (double)S::dec(opp);
+        double q = 0.5, ud[3] = {0.0, 0.0, 0.0};
+        if (!w) body_cut(I, x, y, z, cx(i), cy(i), cz<Q>(i), t1, q, ud);
+        s_q[g][i] = q;
+        for (int a = 0; a < 3; ++a) s_uw[g][i][a] = ud[a];
+      }
+    }
+    __syncthreads();
+    const uint32_t miss = s_miss[g];
+    // ---- lagged fields of the neighbours needed ---------------------------
+    // (x itself; x + c_i and x + 2 c_i for the missing i and for the axis
+    // directions.)  The flag and the Q populations are loaded together.
+    if (active && lane < NS) {
+      bool need;
+      int off[3] = {0, 0, 0};
+      if (lane == 0) {
+        need = miss != 0u;
+      } else {
+        const int j = (lane - 1) >> 1, kk = ((lane - 1) & 1) + 1;
+        const int i = j < rest<Q>() ? j : j + 1;
+        off[0] = kk * cx(i);
+        off[1] = kk * cy(i);
+        off[2] = kk * cz<Q>(i);
+        need = miss && (((miss >> i) & 1u) || nnz<Q>(i) == 1);
+      }
+      int fluid = 0;
+      uint32_t m;
+      if (need && resolve_nb(I, x, y, z, off[0], off[1], off[2], m)) {
+        const uint8_t fs = fl[m];
+        T v[Q];
+#pragma unroll
+        for (int p = 0; p < Q; ++p) v[p] = sb[p * stride + m];
+        if (lane == 0 || !(fs & FLAG_SOLID)) {
+          double rt = 0.0, j3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+          for (int p = 0; p < Q; ++p) {
+            const double dv = (double)S::dec(v[p]);
+            rt += dv;
+            if (cx(p) > 0) j3[0] += dv;
+            if (cx(p) < 0) j3[0] -= dv;
+            if (cy(p) > 0) j3[1] += dv;
+            if (cy(p) < 0) j3[1] -= dv;
+            if (cz<Q>(p) > 0) j3[2] += dv;
+            if (cz<Q>(p) < 0) j3[2] -= dv;
+          }
+          const double ir = 1.0 / (1.0 + rt);
+          s_lr[g][lane] = rt;
+          for (int a = 0; a < 3; ++a) s_lu[g][lane][a] = j3[a] * ir;
+          fluid = 1;
+        }
+      }
+      s_lf[g][lane] = fluid;
+    }
+    __syncthreads();
+    // ---- Grad target values (lane 0) ---------------------------------------
+    if (active && lane == 0 && miss) {
+      const double rho_n = 1.0 + s_lr[g][0];
+      double rtt = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        if (!((miss >> i) & 1u)) {
+          rtt += s_f[g][i];
+        } else {
+          const double cu = cx(i) * s_uw[g][i][0] + cy(i) * s_uw[g][i][1] + cz<Q>(i) * s_uw[g][i][2];
+          rtt += s_opp[g][i] + 6.0 * weight<Q>(i) * rho_n * cu;
+        }
+      }
+      const double rho_t = 1.0 + rtt;
+      double ut0 = 0.0, ut1 = 0.0, ut2 = 0.0;
+      int nm = 0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        if (!((miss >> i) & 1u)) continue;
+        const double q = s_q[g][i];
+        const int l1 = lag_slot<Q>(i, 1), l2 = lag_slot<Q>(i, 2);
+        const double w0 = s_uw[g][i][0], w1 = s_uw[g][i][1], w2 = s_uw[g][i][2];
+        if (s_lf[g][l1] && s_lf[g][l2]) {
+          const double a0 = 2.0 / ((1.0 + q) * (2.0 + q));
+          const double a1 = 2.0 * q / (1.0 + q);
+          const double a2 = -q / (2.0 + q);
+          ut0 += a0 * w0 + a1 * s_lu[g][l1][0] + a2 * s_lu[g][l2][0];
+          ut1 += a0 * w1 + a1 * s_lu[g][l1][1] + a2 * s_lu[g][l2][1];
+          ut2 += a0 * w2 + a1 * s_lu[g][l1][2] + a2 * s_lu[g][l2][2];
+        } else if (s_lf[g][l1]) {
+          ut0 += (w0 + q * s_lu[g][l1][0]) / (1.0 + q);
+          ut1 += (w1 + q * s_lu[g][l1][1]) / (1.0 + q);
+          ut2 += (w2 + q * s_lu[g][l1][2]) / (1.0 + q);
+        } else {
+          ut0 += w0;
+          ut1 += w1;
+          ut2 += w2;
+        }
+        ++nm;
+      }
+      ut0 /= nm;
+      ut1 /= nm;
+      ut2 /= nm;
+      // G[a][b] = d u_a / d x_b, as in gather_pre.
+      double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+      for (int bb = 0; bb < D; ++bb) {
+        const int ip = axis_pop<Q>(bb, +1);   // c = +e_b: slots x + e_b, x + 2 e_b
+        const int im = axis_pop<Q>(bb, -1);   // c = -e_b
+        const bool cut_m = (miss >> ip) & 1u, cut_p = (miss >> im) & 1u;
+        const int p1 = lag_slot<Q>(ip, 1), p2 = lag_slot<Q>(ip, 2);
+        const int m1 = lag_slot<Q>(im, 1), m2 = lag_slot<Q>(im, 2);
+        const bool fp1 = s_lf[g][p1], fp2 = fp1 && s_lf[g][p2];
+        const bool fm1 = s_lf[g][m1], fm2 = fm1 && s_lf[g][m2];
+        const double qm = cut_m ? s_q[g][ip] : 0.0, qp = cut_p ? s_q[g][im] : 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const double wm = cut_m ? s_uw[g][ip][a] : 0.0, wp = cut_p ? s_uw[g][im][a] : 0.0;
+          const double up1 = fp1 ? s_lu[g][p1][a] : 0.0, up2 = fp2 ? s_lu[g][p2][a] : 0.0;
+          const double um1 = fm1 ? s_lu[g][m1][a] : 0.0, um2 = fm2 ? s_lu[g][m2][a] : 0.0;
+          double gr = 0.0;
+          if (cut_m && cut_p) {
+            gr = (wp - wm) / (qp + qm);
+          } else if (cut_m) {
+            if (fp2)
+              gr = -3.0 * wm / ((1.0 + qm) * (2.0 + qm)) + up1 * (2.0 - qm) / (1.0 + qm) +
+                   up2 * (qm - 1.0) / (2.0 + qm);
+            else if (fp1)
+              gr = (up1 - wm) / (1.0 + qm);
+          } else if (cut_p) {
+            if (fm2)
+              gr = 3.0 * wp / ((1.0 + qp) * (2.0 + qp)) - um1 * (2.0 - qp) / (1.0 + qp) -
+                   um2 * (qp - 1.0) / (2.0 + qp);
+            else if (fm1)
+              gr = (wp - um1) / (1.0 + qp);
+          } else if (fp1 && fm1) {
+            gr = 0.5 * (up1 - um1);
+          } else if (fp1) {
+            gr = up1 - s_lu[g][0][a];
+          } else if (fm1) {
+            gr = s_lu[g][0][a] - um1;
+          }
+          G[a][bb] = gr;
+        }
+      }
+      const double kneq = rho_t / (6.0 * I.beta);
+      s_t[g][0] = rho_t;
+      s_t[g][1] = ut0;
+      s_t[g][2] = ut1;
+      s_t[g][3] = ut2;
+      s_t[g][4] = rho_t / 3.0 + rho_t * ut0 * ut0 - kneq * 2.0 * G[0][0];
+      s_t[g][5] = rho_t / 3.0 + rho_t * ut1 * ut1 - kneq * 2.0 * G[1][1];
+      s_t[g][6] = rho_t / 3.0 + rho_t * ut2 * ut2 - kneq * 2.0 * G[2][2];
+      s_t[g][7] = rho_t * ut0 * ut1 - kneq * (G[0][1] + G[1][0]);
+      s_t[g][8] = rho_t * ut0 * ut2 - kneq * (G[0][2] + G[2][0]);
+      s_t[g][9] = rho_t * ut1 * ut2 - kneq * (G[1][2] + G[2][1]);
+    }
+    __syncthreads();
+    // ---- f* for the missing populations, then the collision ----------------
+    const int i = lane;
+    double d = 0.0;
+    if (active && i < Q) {
+      d = s_f[g][i];
+      if ((miss >> i) & 1u) {
+        const double ut[3] = {s_t[g][1], s_t[g][2], s_t[g][3]};
+        const double Pi[6] = {s_t[g][4], s_t[g][5], s_t[g][6], s_t[g][7], s_t[g][8], s_t[g][9]};
+        d = grad_dev<Q, double>(i, s_t[g][0], ut, Pi);
+      }
+    }
+    const bool pop = active && i < Q;
+    // Moments of the pre-collision state.
+    const double rt = group_sum<GL>(pop ? d : 0.0);
+    const double jx = group_sum<GL>(pop ? cx(i) * d : 0.0);
+    const double jy = group_sum<GL>(pop ? cy(i) * d : 0.0);
+    const double jz = group_sum<GL>(pop ? cz<Q>(i) * d : 0.0);
+    const double rho = 1.0 + rt, ir = 1.0 / rho;
+    const double u[3] = {jx * ir, jy * ir, jz * ir};
+    const bool ok = rho > 0.0 && fabs(u[0]) < 1.0 && fabs(u[1]) < 1.0 && fabs(u[2]) < 1.0;
+    const int c0 = pop ? cx(i) : 0, c1 = pop ? cy(i) : 0, c2 = pop ? cz<Q>(i) : 0;
+    const AxisEq<double> ax = axis_eq(u[0]), ay = axis_eq(u[1]);
+    const AxisEq<double> az = Q == 27 ? axis_eq(u[2]) : ay;
+    double E = pick3(c0, ax.e0, ax.ep, ax.em);
+    {
+      const double ey = pick3(c1, ay.e0, ay.ep, ay.em);
+      E = E + ey + E * ey;
+      if (Q == 27) {
+        const double ez = pick3(c2, az.e0, az.ep, az.em);
+        E = E + ez + E * ez;
+      }
+    }
+    // Delta = f - f^eq, with the mass and momentum rounding left in it moved
+    // to the rest and axis populations (the second moments are unchanged).
+    double dl = pop ? d - weight<Q>(i) * (rt + rho * E) : 0.0;
+    const double rm = group_sum<GL>(dl);
+    const double qx = group_sum<GL>(c0 * dl);
+    const double qy = group_sum<GL>(c1 * dl);
+    const double qz = group_sum<GL>(c2 * dl);
+    const int nz = (c0 != 0) + (c1 != 0) + (c2 != 0);
+    if (pop) {
+      if (nz == 0) dl -= rm;
+      if (nz == 1) dl -= 0.5 * (c0 * qx + c1 * qy + c2 * qz);
+    }
+    // Second moments and the shear part (closed form, as in the bulk).
+    const double Pxx = group_sum<GL>(c0 != 0 ? dl : 0.0);
+    const double Pyy = group_sum<GL>(c1 != 0 ? dl : 0.0);
+    const double Pzz = group_sum<GL>(c2 != 0 ? dl : 0.0);
+    const double Pxy = group_sum<GL>((double)(c0 * c1) * dl);
+    const double Pxz = group_sum<GL>((double)(c0 * c2) * dl);
+    const double Pyz = group_sum<GL>((double)(c1 * c2) * dl);
+    double T, Dxx, Dyy, Dzz;
+    if (Q == 27) {
+      T = Pxx + Pyy + Pzz;
+      Dxx = Pxx - T / 3.0;
+      Dyy = Pyy - T / 3.0;
+      Dzz = -(Dxx + Dyy);
+    } else {
+      T = Pxx + Pyy;
+      Dxx = 0.5 * (Pxx - Pyy);
+      Dyy = -Dxx;
+      Dzz = 0.0;
+    }
+    const double ts = I.trace_in_s ? T : 0.0;
+    double si = 0.0;   // Delta s_i (faces: Dev/2 + T/(2D) with the trace; edges: +-P_ab/4)
+    if (pop) {
+      if (nz == 1) si = 0.5 * (c0 != 0 ? Dxx : (c1 != 0 ? Dyy : Dzz)) + ts * (0.5 / D);
+      else if (nz == 2) si = 0.25 * (c0 * c1 * Pxy + c0 * c2 * Pxz + c1 * c2 * Pyz);
+      else if (nz == 0) si = -ts;
+    }
+    const double hi = dl - si;
+    double inv = 0.0;   // 1 / f^eq_i
+    if (pop) {
+      inv = ir * pick3(c0, ax.g0, ax.gp, ax.gm) * pick3(c1, ay.g0, ay.gp, ay.gm);
+      if (Q == 27) inv *= pick3(c2, az.g0, az.gp, az.gm);
+    }
+    const double aa = group_sum<GL>(si * hi * inv);
+    const double bb = group_sum<GL>(hi * hi * inv);
+    double gamma = 2.0;
+    if (!I.collision && bb > 1e-300) gamma = 1.0 / I.beta - (2.0 - 1.0 / I.beta) * aa / bb;
+    if (pop) {
+      const double outv = ok ? d - I.beta * (2.0 * si + gamma * hi) : d;
+      db[i * stride + me] = S::enc_d(outv);
+    }
+    if (active && lane == 0) {
+      if (!ok) atomicOr(b.err, 1u);
+      const float gf = ok ? (float)gamma : 2.0f;
+      gmin = fminf(gmin, gf);
+      gmax = fmaxf(gmax, gf);
+      gsum += gf;
+      cnt += 1;
+      f64 += 1;
+    }
+    __syncthreads();
+  }
+  if (b.stats) block_stats<64>(gmin, gmax, gsum, cnt, f64, b.stats + stat0 + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -662,9 +1079,11 @@ __global__ void __launch_bounds__(256) k_neq_fixup(StepBuffers b, int stat0) {
   using R = typename S::R;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     // End of the step: the next step appends to the other counter, which no
-    // kernel of this step reads; only the geometry and boundary kernels,
-    // which ran before, read the clock.
+    // kernel of this step reads; the boundary lists were consumed before;
+    // only the geometry and boundary kernels, which ran before, read the
+    // clock.
     *b.neq_next = 0u;
+    for (int j = 0; j < b.nbcount; ++j) b.bcount[j] = 0u;
     if (b.clock_tick) *b.clock_tick += 1;
   }
   const uint32_t n = min(*b.neq_count, b.neq_cap);
@@ -1036,13 +1455,20 @@ static hipError_t launch_bulk(int v, const StepBuffers& b, const Tile* tiles, in
 
 template <int Q, int ST>
 static hipError_t launch_boundary(const StepBuffers& b, const Region* regions,
-                                  const BoxTile* btiles, int bt0, int nbt, int stat0,
+                                  const BoxTile* btiles, int bt0, int nbt, uint2* list,
+                                  uint32_t cap, uint32_t* count, int nwg, int nfb, int stat0,
                                   hipStream_t s) {
-  if (nbt <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_boundary<Q, ST>), dim3(nbt), dim3(256), 0, s, b, regions, btiles, bt0,
+  if (nbt <= 0 || nwg <= 0 || nfb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_boundary_scan<Q>), dim3(nbt), dim3(256), 0, s, b.insts, regions, btiles,
+                     bt0, b.flags, list, cap, count);
+  hipLaunchKernelGGL((k_boundary_face<Q, ST>), dim3(nfb), dim3(256), 0, s, b, list + cap,
+                     count + 1, cap, stat0 + nwg);
+  hipLaunchKernelGGL((k_boundary_wave<Q, ST>), dim3(nwg), dim3(64), 0, s, b, list, count, cap,
                      stat0);
   return hipGetLastError();
 }
+
+int boundary_nodes_per_workgroup(int Q) { return Q == 27 ? 1 : 2; }
 
 template <int Q, int ST>
 static hipError_t launch_geometry(int stage, const InstDev* insts, const Region* regions,

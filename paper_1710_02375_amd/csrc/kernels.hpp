@@ -35,6 +35,8 @@ struct StepBuffers {
   uint32_t neq_cap;
   uint32_t* neq_next;     // the next step's counter, cleared by the FP64 pass
   int64_t* clock_tick;    // advanced by one at the end of the step, or null
+  uint32_t* bcount;       // boundary-list counters, cleared by the FP64 pass
+  int nbcount;
 };
 
 struct Ops {
@@ -42,11 +44,16 @@ struct Ops {
   // special flag.  Statistics go to stats[tile index].
   hipError_t (*bulk)(int variant, const StepBuffers& b, const Tile* tiles, int tile0, int ntiles,
                      hipStream_t s);
-  // Special nodes (faces, cut links) of the scanned regions: streaming with
-  // Grad fill and face conditions, then collision.  Statistics go to
-  // stats[stat0 + box tile index].
+  // Special nodes (faces, cut links) of the scanned box tiles [bt0, bt0+nbt):
+  // a scan appends the nodes with missing populations to list[0, cap) through
+  // count[0] and the inflow / outflow plane nodes to list[cap, 2 cap) through
+  // count[1]; then nwg one-wavefront workgroups stream the first with Grad's
+  // approximation and nfb workgroups of 256 threads the second with the face
+  // equilibria, and both collide.  Both counts must be zero on entry (the
+  // FP64 pass clears them).  Statistics go to stats[stat0, stat0 + nwg + nfb).
   hipError_t (*boundary)(const StepBuffers& b, const Region* regions, const BoxTile* btiles,
-                         int bt0, int nbt, int stat0, hipStream_t s);
+                         int bt0, int nbt, uint2* list, uint32_t cap, uint32_t* count, int nwg,
+                         int nfb, int stat0, hipStream_t s);
   // Geometry update over the swept boxes at time clock + toff:
   // stage 0 marks SOLID_NEXT, stage 1 refills fresh nodes of src, stage 2
   // makes SOLID_NEXT current and marks the cut-link (BODY) nodes.
@@ -79,6 +86,9 @@ struct Ops {
 };
 
 const Ops* get_ops(int Q, int storage);
+
+// Boundary nodes handled by one workgroup (wavefront) at a time.
+int boundary_nodes_per_workgroup(int Q);
 
 // Bulk-kernel variants (workgroup size, nodes per tile, waves per SIMD hint).
 int bulk_variant_count();
