@@ -21,7 +21,7 @@
 using namespace kbc;
 
 // Workgroups of the FP64 pass over deferred near-equilibrium nodes.
-static constexpr int kFixupBlocks = 128;
+static constexpr int kFixupBlocks = 512;
 // Upper bound on the one-wavefront workgroups of a boundary launch.
 static constexpr int kBoundaryWorkgroups = 4096;
 
@@ -1090,6 +1090,14 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int* chosen) {
   for (int v = 0; v < bulk_variant_count(); ++v) {
     if (bulk_variant_off32(v) && !fits_off32(c)) continue;
     if ((st = lbm_set_variant(c, v))) break;
+    // Every candidate starts from the saved state, so that all are timed on
+    // the same flow (a developing flow changes the boundary and FP64 work).
+    HIPCHECK(c, hipMemcpyAsync(c->buf[cur0], save, pbytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(c->flags, fsave, c->flag_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(c->dclock, &step0, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    c->cur = cur0;
+    c->step = step0;
     if ((st = lbm_step(c, 2))) break;
     HIPCHECK(c, hipEventRecord(e0, c->stream));
     if ((st = lbm_step(c, 6))) break;

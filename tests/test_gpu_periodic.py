@@ -258,6 +258,37 @@ def test_checkpoint_resume_is_bitwise():
     assert np.array_equal(b.get_populations(), ref)
 
 
+def test_autotune_restores_state_and_variants_agree_bitwise():
+    """The autotuner times every bulk variant from the saved state and puts
+    it back: the state, the clock (inflow ramp, body motion) and the next
+    steps are those of a context that was never tuned.  Variants differ only
+    in launch shape and addressing, so results agree bitwise."""
+    from paper_1710_02375_amd import lbm
+
+    n = 24
+    say("case: autotune restores state, channel with sphere D3Q27 F32 n=%d" % n)
+    cfg = W.sphere_channel(2 * n, n, n, radius=4.0, amplitude=1.0, period=200.0, ramp=20)
+    kind, p = cfg["body"]
+    desc = dict(Q=27, nx=2 * n, ny=n, nz=n, nu=cfg["nu"], storage="f32", faces=cfg["faces"],
+                u_in=cfg["u_in"], ramp_steps=cfg["ramp_steps"])
+    N = 2 * n * n * n
+    outs = []
+    for tune in (False, True):
+        s = lbm.Solver([desc])
+        s.init_fields(np.ones(N), np.zeros((3, N)))
+        s.set_body(kind, p)
+        s.step(5)
+        before = s.get_populations()
+        if tune:
+            v = lbm.lbm_autotune(s.ctx, None)
+            say("  chosen variant %s" % lbm.lbm_variant_name(v))
+            assert np.array_equal(s.get_populations(), before)
+        s.step(7)
+        outs.append(s.get_populations())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_nonfinite_state_reported():
     from paper_1710_02375_amd import lbm
 
