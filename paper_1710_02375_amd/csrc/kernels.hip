@@ -408,7 +408,31 @@ __device__ void block_stats(float gmin, float gmax, double gsum, uint32_t cnt, u
 // MEM bit 0: non-temporal stores; bit 1: non-temporal loads; bit 2: 32-bit
 // byte offsets from one base per instance (every instance's Q population
 // arrays span less than 4 GiB), which removes the 64-bit address arithmetic
-// and the per-population base registers.
+// and the per-population base registers; bit 3 (with bit 2): buffer loads and
+// stores through one resource per instance and buffer, the population offset
+// i * stride in the scalar offset, so that a load or store needs no vector
+// address arithmetic beyond the node's own offset.
+// AUX: cache policy bits of the instruction (2 = non-temporal).
+template <typename T, int AUX>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 2)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, AUX));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
+}
+
+template <typename T, int AUX>
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                          uint32_t soff) {
+  if constexpr (sizeof(T) == 2)
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff, AUX);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, AUX);
+}
+
+// Buffer resource word 3 for gfx9-family targets (raw, untyped 32-bit data).
+constexpr int kBufferWord3 = 0x00020000;
+
 template <int Q, int ST, int BLOCK, int WAVES, int MEM, bool STATS>
 __global__ void __launch_bounds__(BLOCK, WAVES)
     k_bulk(StepBuffers b, const Tile* __restrict__ tiles, int tile0) {
@@ -453,9 +477,23 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
       zp = (uint32_t)(c.z == nz - 1 ? 0 : c.z + 1) * plane;
     }
     T raw[Q];
-    if (MEM & 4) {
-      constexpr uint32_t es = sizeof(T);
-      const uint32_t pstride = (uint32_t)stride * es;
+    constexpr bool BUF = (MEM & 8) && sizeof(T) <= 4;
+    constexpr uint32_t es = sizeof(T);
+    const uint32_t pbytes = (uint32_t)stride * es;
+    if constexpr (BUF) {
+      // Byte offsets within the instance's populations: node part in the
+      // vector offset, population part (i * stride) in the scalar offset.
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<T*>(sb), (short)0, (int)(uint32_t)(Q * pbytes), kBufferWord3);
+      const uint32_t bx[3] = {xp * es, (uint32_t)c.x * es, xm * es};   // by -cx + 1
+      const uint32_t byz[3] = {yp * es, y0 * es, ym * es};
+      const uint32_t bz[3] = {zp * es, z0 * es, zm * es};
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        raw[i] = buf_load<T, (MEM & 2) ? 2 : 0>(
+            rs, bx[cx(i) + 1] + byz[cy(i) + 1] + bz[cz<Q>(i) + 1], (uint32_t)i * pbytes);
+    } else if (MEM & 4) {
+      const uint32_t pstride = pbytes;
       const uint32_t bx[3] = {xp * es, (uint32_t)c.x * es, xm * es};   // by -cx + 1
       const uint32_t byz[3] = {yp * es, y0 * es, ym * es};
       const uint32_t bz[3] = {zp * es, z0 * es, zm * es};
@@ -484,13 +522,21 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
     for (int i = 0; i < Q; ++i) f[i] = S::dec(raw[i]);
     CollideOut co;
     if (!collide<Q, R, true>(f, P, co)) atomicOr(b.err, 1u);
+    if constexpr (BUF) {
+      const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+          db, (short)0, (int)(uint32_t)(Q * pbytes), kBufferWord3);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      T* p = (MEM & 4) ? reinterpret_cast<T*>(reinterpret_cast<char*>(db) +
-                                                ((uint32_t)i * (uint32_t)stride + node) *
-                                                    (uint32_t)sizeof(T))
-                       : db + (i * stride + node);
-      if (MEM & 1) __builtin_nontemporal_store(S::enc(f[i]), p); else *p = S::enc(f[i]);
+      for (int i = 0; i < Q; ++i)
+        buf_store<T, (MEM & 1) ? 2 : 0>(S::enc(f[i]), rd, node * es, (uint32_t)i * pbytes);
+    } else {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        T* p = (MEM & 4) ? reinterpret_cast<T*>(reinterpret_cast<char*>(db) +
+                                                  ((uint32_t)i * (uint32_t)stride + node) *
+                                                      (uint32_t)sizeof(T))
+                         : db + (i * stride + node);
+        if (MEM & 1) __builtin_nontemporal_store(S::enc(f[i]), p); else *p = S::enc(f[i]);
+      }
     }
     // Near-equilibrium nodes go to the FP64 pass; one atomic per wave.
     const uint64_t m = __ballot(co.fp64 != 0);
@@ -1409,7 +1455,9 @@ static const BulkVariant kVariants[] = {
     {"b256_t1024_w2_nts", 256, 1024, 2, 1},   {"b512_t512_w1_ntls", 512, 512, 1, 3},
     {"b256_t1024_w2_ntls", 256, 1024, 2, 3},  {"b512_t512_w1_nts_o32", 512, 512, 1, 5},
     {"b256_t256_w2_nts_o32", 256, 256, 2, 5}, {"b256_t1024_w2_nts_o32", 256, 1024, 2, 5},
-    {"b256_t256_w1_o32", 256, 256, 1, 4},
+    {"b256_t256_w1_o32", 256, 256, 1, 4},     {"b512_t512_w1_buf", 512, 512, 1, 12},
+    {"b512_t512_w1_nts_buf", 512, 512, 1, 13}, {"b256_t256_w2_nts_buf", 256, 256, 2, 13},
+    {"b256_t1024_w2_nts_buf", 256, 1024, 2, 13},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -1449,6 +1497,10 @@ static hipError_t launch_bulk(int v, const StepBuffers& b, const Tile* tiles, in
     case 12: return launch_bulk_v<Q, ST, 256, 2, 5>(b, tiles, tile0, ntiles, s);
     case 13: return launch_bulk_v<Q, ST, 256, 2, 5>(b, tiles, tile0, ntiles, s);
     case 14: return launch_bulk_v<Q, ST, 256, 1, 4>(b, tiles, tile0, ntiles, s);
+    case 15: return launch_bulk_v<Q, ST, 512, 1, 12>(b, tiles, tile0, ntiles, s);
+    case 16: return launch_bulk_v<Q, ST, 512, 1, 13>(b, tiles, tile0, ntiles, s);
+    case 17: return launch_bulk_v<Q, ST, 256, 2, 13>(b, tiles, tile0, ntiles, s);
+    case 18: return launch_bulk_v<Q, ST, 256, 2, 13>(b, tiles, tile0, ntiles, s);
     default: return launch_bulk_v<Q, ST, 256, 1, 0>(b, tiles, tile0, ntiles, s);
   }
 }
