@@ -46,17 +46,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(nodes):
-    """HBM bytes per launch of the bulk kernel from the committed rocprofv3
-    counter summary (lines "key: value"), or None if it is missing, was taken
-    on a different kernel source, or on a different lattice size."""
+def read_traffic(nodes, variant):
+    """HBM bytes per launch of the bulk kernel variant from the committed
+    rocprofv3 counter summary (lines "key: value", per variant
+    "hbm_bytes_per_launch[<variant>]"), or None if it is missing, was taken on
+    a different kernel source, a different lattice size or another variant."""
     try:
         with open(TRAFFIC_FILE) as f:
             kv = dict(l.split(":", 1) for l in f if ":" in l and not l.startswith("#"))
         kv = {k.strip(): v.strip() for k, v in kv.items()}
         if kv.get("kernel_source_hash") != kernel_source_hash() or int(kv.get("nodes", 0)) != nodes:
             return None
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv["hbm_bytes_per_launch[%s]" % variant])
     except (OSError, ValueError, KeyError):
         return None
 
@@ -354,7 +355,7 @@ def main():
                                      args.warmup, args.variant)
     bytes_per_lup = info["bytes_per_update"]
     achieved = bytes_per_lup * n ** 3 / (kms * 1e-3) / 1e9
-    traffic = read_traffic(n ** 3)
+    traffic = read_traffic(n ** 3, info["variant"])
     result = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),

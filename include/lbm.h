@@ -194,9 +194,12 @@ lbm_status lbm_set_stats(lbm_ctx* ctx, int enabled);
 lbm_status lbm_set_launch_mode(lbm_ctx* ctx, int mode);
 
 /* Times the candidate tile shapes of the bulk kernel on this context's
- * instances (a few steps each, state restored afterwards) and keeps the
- * fastest.  cache_path (nullable) names a JSON file of earlier results keyed
- * by lattice, storage, sizes and device; it is read first and updated.
+ * instances (18 steps each from the same saved state) and keeps the fastest.
+ * Both population buffers, the flags and the clock are restored afterwards,
+ * so the following steps are bitwise those of an untuned context; the call
+ * needs device memory for two more population buffers while it runs.
+ * cache_path (nullable) names a JSON file of earlier results keyed by
+ * lattice, storage, sizes and device; it is read first and updated.
  * chosen (nullable) receives the index of the chosen variant. */
 lbm_status lbm_autotune(lbm_ctx* ctx, const char* cache_path, int* chosen);
 

@@ -1072,15 +1072,20 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int* chosen) {
     return LBM_OK;
   }
   HIPCHECK(c, hipStreamSynchronize(c->stream));
-  // Save state, flags and clock; the trial steps are undone afterwards.
+  // Save both population buffers, flags and clock; the trial steps are undone
+  // afterwards.  The other buffer matters too: nodes inside a moving body are
+  // never written while solid, so they keep what was last stored there, and a
+  // trial run moves the body further than the caller has.
   const size_t pbytes = c->pop_elems * c->esize;
-  void* save = nullptr;
+  char* save = nullptr;
   uint8_t* fsave = nullptr;
-  if ((st = dev_alloc(c, pbytes, &save))) return st;
+  if ((st = dev_alloc(c, 2 * pbytes, (void**)&save))) return st;
   if ((st = dev_alloc(c, c->flag_bytes, (void**)&fsave))) { dev_free(c, save); return st; }
-  HIPCHECK(c, hipMemcpyAsync(save, c->buf[c->cur], pbytes, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHECK(c, hipMemcpyAsync(fsave, c->flags, c->flag_bytes, hipMemcpyDeviceToDevice, c->stream));
   const int cur0 = c->cur;
+  HIPCHECK(c, hipMemcpyAsync(save, c->buf[cur0], pbytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHECK(c, hipMemcpyAsync(save + pbytes, c->buf[1 - cur0], pbytes, hipMemcpyDeviceToDevice,
+                             c->stream));
+  HIPCHECK(c, hipMemcpyAsync(fsave, c->flags, c->flag_bytes, hipMemcpyDeviceToDevice, c->stream));
   const int64_t step0 = c->step;
   hipEvent_t e0, e1;
   HIPCHECK(c, hipEventCreate(&e0));
@@ -1100,7 +1105,7 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int* chosen) {
     c->step = step0;
     if ((st = lbm_step(c, 2))) break;
     HIPCHECK(c, hipEventRecord(e0, c->stream));
-    if ((st = lbm_step(c, 6))) break;
+    if ((st = lbm_step(c, 16))) break;
     HIPCHECK(c, hipEventRecord(e1, c->stream));
     HIPCHECK(c, hipEventSynchronize(e1));
     float ms = 0.f;
@@ -1113,6 +1118,8 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int* chosen) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   HIPCHECK(c, hipMemcpyAsync(c->buf[cur0], save, pbytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHECK(c, hipMemcpyAsync(c->buf[1 - cur0], save + pbytes, pbytes, hipMemcpyDeviceToDevice,
+                             c->stream));
   HIPCHECK(c, hipMemcpyAsync(c->flags, fsave, c->flag_bytes, hipMemcpyDeviceToDevice, c->stream));
   HIPCHECK(c, hipMemcpyAsync(c->dclock, &step0, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
   HIPCHECK(c, hipMemsetAsync(c->derr, 0, sizeof(uint32_t), c->stream));
