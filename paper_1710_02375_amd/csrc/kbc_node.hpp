@@ -354,17 +354,18 @@ __device__ __forceinline__ bool collide(R (&d)[Q], const CollideParams<R>& P, Co
   R ex[3] = {A[0].em, A[0].e0, A[0].ep};
   R ey[3] = {A[1].em, A[1].e0, A[1].ep};
   R ez[3] = {A[2].em, A[2].e0, A[2].ep};
-  // rho p_x - w, p_y, p_y - w, p_z, p_z - w
-  R dxr[3], py[3], dy[3], pz[3], dz[3];
+  // rho p_x - w, p_y, p_y - w, p_z - w
+  R dxr[3], py[3], dy[3], dz[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     dxr[k] = wv[k] * (rt + rho * ex[k]);
     dy[k] = wv[k] * ey[k];
     py[k] = wv[k] + dy[k];
     dz[k] = wv[k] * ez[k];
-    pz[k] = wv[k] + dz[k];
   }
   // ---- Delta = f~ - (f^eq - W) ---------------------------------------------
+  // f^eq_i - W_i = dxy p_z + w_a w_b (p_z - w_c) = w_c dxy + pxy (p_z - w_c)
+  // with dxy = rho p_x p_y - w_a w_b and pxy = rho p_x p_y.
   R dl[Q];
 #pragma unroll
   for (int b = 0; b < 3; ++b)
@@ -372,11 +373,11 @@ __device__ __forceinline__ bool collide(R (&d)[Q], const CollideParams<R>& P, Co
     for (int a = 0; a < 3; ++a) {
       const R dxy = dxr[a] * py[b] + wv[a] * dy[b];   // rho p_x p_y - w_a w_b
       if (Q == 27) {
-        const R wab = R(w1d(a - 1) * w1d(b - 1));
+        const R pxy = dxy + R(w1d(a - 1) * w1d(b - 1));
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const int i = a + 3 * b + 9 * c;
-          dl[i] = d[i] - (dxy * pz[c] + wab * dz[c]);
+          dl[i] = (d[i] - wv[c] * dxy) - pxy * dz[c];
         }
       } else {
         const int i = a + 3 * b;
@@ -470,25 +471,32 @@ __device__ __forceinline__ bool collide(R (&d)[Q], const CollideParams<R>& P, Co
     const R gx[3] = {ir * A[0].gm, ir * A[0].g0, ir * A[0].gp};
     const R gy[3] = {A[1].gm, A[1].g0, A[1].gp};
     const R gz[3] = {A[2].gm, A[2].g0, A[2].gp};
+    // 1/f^eq_i = gx(a) gy(b) gz(c): the sums over c of each (a, b) column
+    // are taken first and weighted by gx gy once per column.
     R a = R(0), b = R(0), ss = R(0);
 #pragma unroll
     for (int bb = 0; bb < 3; ++bb)
 #pragma unroll
       for (int aa = 0; aa < 3; ++aa) {
-        const R gxy = gx[aa] * gy[bb];
+        R bc = R(0), ac = R(0), sc = R(0);
 #pragma unroll
         for (int cc = 0; cc < (Q == 27 ? 3 : 1); ++cc) {
           const int i = aa + 3 * bb + 9 * cc;
-          const R inv = (Q == 27) ? gxy * gz[cc] : gxy;   // 1 / f^eq_i
+          const int n = nnz<Q>(i);
+          const bool has_s = n == 1 || n == 2 || n == 0;
           const R si = ds_of(i);
-          const R hi = dl[i] - si;                         // Delta h_i
-          const R hw = hi * inv;
-          b += hw * hi;
-          if (nnz<Q>(i) == 1 || nnz<Q>(i) == 2 || (nnz<Q>(i) == 0)) {
-            a += hw * si;
-            ss += si * si * inv;
+          const R hi = has_s ? dl[i] - si : dl[i];       // Delta h_i
+          const R hz = (Q == 27) ? hi * gz[cc] : hi;
+          bc += hz * hi;
+          if (has_s) {
+            ac += hz * si;
+            sc += (Q == 27) ? si * si * gz[cc] : si * si;
           }
         }
+        const R gxy = gx[aa] * gy[bb];
+        b += gxy * bc;
+        a += gxy * ac;
+        ss += gxy * sc;
       }
     const R dd = ss + R(2) * a + b;   // <Delta|Delta>
     // FP32 cannot resolve gamma when <Delta|Delta> is small against the

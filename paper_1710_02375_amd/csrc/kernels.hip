@@ -444,8 +444,12 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
   // Local copy: read once, not re-read after every store (the compiler cannot
   // prove the descriptor does not alias the populations).
   const InstDev I = b.insts[tl.inst];
-  const int nx = I.nx, ny = I.ny;
-  const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+  const int nx = I.nx, ny = I.ny, nz = I.nz;
+  // Node offsets of one step along y and z, and of the periodic wrap
+  // (n - 1 steps) along each axis.
+  const uint32_t sy = (uint32_t)nx, sz = (uint32_t)nx * (uint32_t)ny;
+  const uint32_t wx = (uint32_t)(nx - 1), wy = (uint32_t)(ny - 1) * sy,
+                 wz = (uint32_t)(nz - 1) * sz;
   const int64_t stride = I.stride;
   const T* __restrict__ sb = static_cast<const T*>(b.src) + I.pop_off;
   T* __restrict__ db = static_cast<T*>(b.dst) + I.pop_off;
@@ -464,52 +468,52 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
     const uint32_t node = (uint32_t)(tl.node0 + k);
     if (fl && (fl[node] & FLAG_SPECIAL)) continue;
     const Coord c = node_coord(I, node);
-    const uint32_t xm = c.x == 0 ? nx - 1 : c.x - 1;
-    const uint32_t xp = c.x == nx - 1 ? 0 : c.x + 1;
-    const uint32_t y0 = (uint32_t)c.y * nx;
-    const uint32_t ym = (uint32_t)(c.y == 0 ? ny - 1 : c.y - 1) * nx;
-    const uint32_t yp = (uint32_t)(c.y == ny - 1 ? 0 : c.y + 1) * nx;
-    uint32_t z0 = 0, zm = 0, zp = 0;
-    if (Q == 27) {
-      const int nz = I.nz;
-      z0 = (uint32_t)c.z * plane;
-      zm = (uint32_t)(c.z == 0 ? nz - 1 : c.z - 1) * plane;
-      zp = (uint32_t)(c.z == nz - 1 ? 0 : c.z + 1) * plane;
-    }
+    // Source of population i is node - c_i, wrapped periodically: per axis
+    // the node offset of the neighbour at -1 (dm) and +1 (dp), modulo 2^32,
+    // chosen between two per-instance constants (no per-node products).
+    const uint32_t dm[3] = {c.x == 0 ? wx : 0u - 1u, c.y == 0 ? wy : 0u - sy,
+                            c.z == 0 ? wz : 0u - sz};
+    const uint32_t dp[3] = {c.x == nx - 1 ? 0u - wx : 1u, c.y == ny - 1 ? 0u - wy : sy,
+                            c.z == nz - 1 ? 0u - wz : sz};
+    // Node offset of the source of (cx, cy, cz): the -c part of each axis.
+    auto dof = [&](int a, int ci) -> uint32_t { return ci == 0 ? 0u : (ci > 0 ? dm[a] : dp[a]); };
     T raw[Q];
     constexpr bool BUF = (MEM & 8) && sizeof(T) <= 4;
     constexpr uint32_t es = sizeof(T);
     const uint32_t pbytes = (uint32_t)stride * es;
-    if constexpr (BUF) {
-      // Byte offsets within the instance's populations: node part in the
-      // vector offset, population part (i * stride) in the scalar offset.
-      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<T*>(sb), (short)0, (int)(uint32_t)(Q * pbytes), kBufferWord3);
-      const uint32_t bx[3] = {xp * es, (uint32_t)c.x * es, xm * es};   // by -cx + 1
-      const uint32_t byz[3] = {yp * es, y0 * es, ym * es};
-      const uint32_t bz[3] = {zp * es, z0 * es, zm * es};
+    if constexpr (BUF || (MEM & 4)) {
+      // Byte offsets within the instance's populations: the (cy, cz) part is
+      // formed once per pair, then each x neighbour adds its own.
+      const uint32_t base = node * es;
+      uint32_t yz[3][3];
 #pragma unroll
-      for (int i = 0; i < Q; ++i)
-        raw[i] = buf_load<T, (MEM & 2) ? 2 : 0>(
-            rs, bx[cx(i) + 1] + byz[cy(i) + 1] + bz[cz<Q>(i) + 1], (uint32_t)i * pbytes);
-    } else if (MEM & 4) {
-      const uint32_t pstride = pbytes;
-      const uint32_t bx[3] = {xp * es, (uint32_t)c.x * es, xm * es};   // by -cx + 1
-      const uint32_t byz[3] = {yp * es, y0 * es, ym * es};
-      const uint32_t bz[3] = {zp * es, z0 * es, zm * es};
+      for (int jy = -1; jy <= 1; ++jy)
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const uint32_t off = (uint32_t)i * pstride + bx[cx(i) + 1] + byz[cy(i) + 1] + bz[cz<Q>(i) + 1];
-        const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(sb) + off);
-        raw[i] = (MEM & 2) ? __builtin_nontemporal_load(p) : *p;
+        for (int jz = -1; jz <= 1; ++jz)
+          yz[jy + 1][jz + 1] = base + (dof(1, jy) + (Q == 27 ? dof(2, jz) : 0u)) * es;
+      const uint32_t xb[3] = {dp[0] * es, 0u, dm[0] * es};   // by cx + 1
+      if constexpr (BUF) {
+        // Node part in the vector offset, population part (i * stride) in
+        // the scalar offset.
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<T*>(sb), (short)0, (int)(uint32_t)(Q * pbytes), kBufferWord3);
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          raw[i] = buf_load<T, (MEM & 2) ? 2 : 0>(
+              rs, yz[cy(i) + 1][cz<Q>(i) + 1] + xb[cx(i) + 1], (uint32_t)i * pbytes);
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const uint32_t off = (uint32_t)i * pbytes + yz[cy(i) + 1][cz<Q>(i) + 1] + xb[cx(i) + 1];
+          const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(sb) + off);
+          raw[i] = (MEM & 2) ? __builtin_nontemporal_load(p) : *p;
+        }
       }
     } else {
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const uint32_t sx = cx(i) == 0 ? (uint32_t)c.x : (cx(i) > 0 ? xm : xp);
-        const uint32_t sy = cy(i) == 0 ? y0 : (cy(i) > 0 ? ym : yp);
-        const uint32_t sz = cz<Q>(i) == 0 ? z0 : (cz<Q>(i) > 0 ? zm : zp);
-        const T* p = sb + (i * stride + (sx + sy + sz));
+        const uint32_t src = node + dof(0, cx(i)) + dof(1, cy(i)) + (Q == 27 ? dof(2, cz<Q>(i)) : 0u);
+        const T* p = sb + (i * stride + src);
         raw[i] = (MEM & 2) ? __builtin_nontemporal_load(p) : *p;
       }
     }

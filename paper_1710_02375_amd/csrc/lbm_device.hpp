@@ -94,11 +94,8 @@ struct Store<LBM_BF16_SHIFTED> {
   using R = float;
   static constexpr int bytes = 2;
   __device__ static R dec(T v) { return __uint_as_float((uint32_t)v << 16); }
-  __device__ static T enc(R v) {
-    const uint32_t b = __float_as_uint(v);
-    if ((b & 0x7fffffffu) > 0x7f800000u) return (T)((b >> 16) | 0x40u);   // quiet NaN
-    return (T)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
-  }
+  // Nearest even; one conversion instruction on this target (NaN stays NaN).
+  __device__ static T enc(R v) { return __builtin_bit_cast(T, (__bf16)v); }
   // One rounding from FP64: round the binary64 significand to 8 bits
   // (nearest even), after which the conversion to binary32 and the bf16
   // truncation are exact (normal range).
@@ -111,11 +108,15 @@ struct Store<LBM_BF16_SHIFTED> {
 };
 
 // ---------------------------------------------------------------------------
-// Division by a run-time invariant d < 2^32 for n < 2^32:
-// q = floor(n * M / 2^64) with M = floor((2^64 - 1) / d) + 1 (d >= 2).
+// Division by a run-time invariant d >= 1 for n < 2^31 (node indices of an
+// instance stay below 2^31).  With l = ceil(log2 d) and M = ceil(2^(31+l)/d),
+// which is below 2^32, floor(n/d) = floor(n M / 2^(31+l)): the excess
+// M d - 2^(31+l) is below d <= 2^l, so n times it stays below 2^(31+l).  On
+// the device that is one 32-bit high multiply and a shift by l - 1.
 // ---------------------------------------------------------------------------
 struct FastDiv {
-  uint64_t M;
+  uint32_t M;
+  uint32_t shift;
   uint32_t d;
   uint32_t pad;
 };
@@ -124,12 +125,19 @@ inline FastDiv make_fastdiv(uint32_t d) {
   FastDiv f;
   f.d = d;
   f.pad = 0;
-  f.M = d <= 1 ? 0 : (~0ull / d) + 1ull;
+  f.M = 0;
+  f.shift = 0;
+  if (d >= 2) {
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    f.M = (uint32_t)(((uint64_t(1) << (31 + l)) + d - 1) / d);
+    f.shift = l - 1;
+  }
   return f;
 }
 
 __device__ __forceinline__ uint32_t fdiv_u32(uint32_t n, const FastDiv& f) {
-  return f.d <= 1 ? n : (uint32_t)__umul64hi((uint64_t)n, f.M);
+  return f.d <= 1 ? n : __umulhi(n, f.M) >> f.shift;
 }
 
 // ---------------------------------------------------------------------------
