@@ -183,10 +183,11 @@ lbm_status lbm_get_populations(lbm_ctx* ctx, int inst, double* f);
 lbm_status lbm_set_populations(lbm_ctx* ctx, int inst, const double* f);
 
 /* Switches per-step statistics (gamma min/mean/max, FP64-path share) on or
- * off; off by default because it adds a reduction to every step.  Boundary
- * nodes (faces, cut links) are collided in FP64 and count as FP64-path nodes;
- * in contexts with several instances, the statistics of an instance cover
- * its bulk nodes only. */
+ * off; off by default because it adds a reduction to every step.  Nodes with
+ * missing populations are collided in FP64 and count as FP64-path nodes;
+ * inflow / outflow face nodes hold an exact equilibrium, whose collision is
+ * the identity, and count with gamma = 2; in contexts with several
+ * instances, the statistics of an instance cover its bulk nodes only. */
 lbm_status lbm_set_stats(lbm_ctx* ctx, int enabled);
 
 /* Launch mode: 0 = one batched launch per kernel for all instances (default),

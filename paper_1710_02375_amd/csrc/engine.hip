@@ -317,7 +317,7 @@ lbm_status rebuild_work(lbm_ctx* c) {
       return (int)std::min<uint64_t>(kBoundaryWorkgroups, (cap + ng - 1) / ng);
     };
     auto nfb_for = [&](uint32_t cap) {
-      return (int)std::min<uint64_t>(kBoundaryWorkgroups / 4, (cap + 255) / 256);
+      return (int)std::min<uint64_t>(kBoundaryWorkgroups, (cap + 63) / 64);
     };
     c->bl_off.assign(c->n_inst, 0);
     c->bl_cap.assign(c->n_inst, 0);

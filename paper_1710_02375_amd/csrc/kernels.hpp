@@ -48,8 +48,9 @@ struct Ops {
   // a scan appends the nodes with missing populations to list[0, cap) through
   // count[0] and the inflow / outflow plane nodes to list[cap, 2 cap) through
   // count[1]; then nwg one-wavefront workgroups stream the first with Grad's
-  // approximation and nfb workgroups of 256 threads the second with the face
-  // equilibria, and both collide.  Both counts must be zero on entry (the
+  // approximation and collide them, and nfb workgroups of 64 threads write
+  // the face equilibria (their collision is the identity).  Both counts must
+  // be zero on entry (the
   // FP64 pass clears them).  Statistics go to stats[stat0, stat0 + nwg + nfb).
   hipError_t (*boundary)(const StepBuffers& b, const Region* regions, const BoxTile* btiles,
                          int bt0, int nbt, uint2* list, uint32_t cap, uint32_t* count, int nwg,
