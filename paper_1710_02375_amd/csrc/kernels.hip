@@ -454,6 +454,7 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
   const T* __restrict__ sb = static_cast<const T*>(b.src) + I.pop_off;
   T* __restrict__ db = static_cast<T*>(b.dst) + I.pop_off;
   const uint8_t* fl = I.flag_off >= 0 ? b.flags + I.flag_off : nullptr;
+  const uint32_t fmask = fl ? uint32_t(FLAG_SPECIAL) : 0u;
   CollideParams<R> P;
   P.beta = (R)I.beta;
   P.inv_beta = (R)(1.0 / I.beta);
@@ -466,7 +467,14 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
   uint32_t cnt = 0, f64 = 0;
   for (int k = threadIdx.x; k < tl.count; k += BLOCK) {
     const uint32_t node = (uint32_t)(tl.node0 + k);
-    if (fl && (fl[node] & FLAG_SPECIAL)) continue;
+    // The flag is loaded with the pulls and tested after them, so that it
+    // adds no memory latency of its own; the pulls of a special node wrap
+    // periodically like any other and stay inside the instance.  The load is
+    // the aligned 32-bit word holding the node's flag byte (flag slices are
+    // padded to 256 bytes); without flags it reads the pool's first word and
+    // the mask is zero, so there is no branch before the pulls.
+    uint32_t fw = *reinterpret_cast<const uint32_t*>(fl ? fl + (node & ~3u) : b.flags);
+    const uint32_t fshift = (node & 3u) * 8u;
     const Coord c = node_coord(I, node);
     // Source of population i is node - c_i, wrapped periodically: per axis
     // the node offset of the neighbour at -1 (dm) and +1 (dp), modulo 2^32,
@@ -521,6 +529,10 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
     // scheduler consumes each value right after its load and a wave keeps a
     // single load in flight.
     __builtin_amdgcn_sched_barrier(0);
+    // An empty statement that the compiler must assume changes fw: the test
+    // cannot be moved above it, to right after the flag load.
+    asm volatile("" : "+v"(fw));
+    if ((fw >> fshift) & fmask) continue;
     R f[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = S::dec(raw[i]);
