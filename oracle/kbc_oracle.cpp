@@ -16,8 +16,12 @@
 //   pinned          -- checked in tests against values fixed by the paper or
 //                      by mathematics (closed forms, invariants, brute force);
 //   parity unpinned -- only self-consistency and physical sanity checks exist
-//                      (Grad target values, fresh-node fill, stress
-//                      extrapolation to surface points).
+//                      (the linear fallback of the Grad target velocity, the
+//                      central-difference factor of the target gradient, the
+//                      density average of the fresh-node fill).  The other
+//                      boundary formulas are pinned by flows with exact
+//                      answers (Couette at q != 1/2, Poiseuille wall traction,
+//                      a body carried by a uniform flow).
 //
 // Lattice conventions: velocities c_i in {-1,0,1}^D with index
 // i = (cx+1) + 3(cy+1) + 9(cz+1), opposite direction Q-1-i, weights the tensor
@@ -514,7 +518,8 @@ void step_once(Domain& d) {
 
   // 2. Fresh nodes (solid at n, fluid at n+1): A := f^eq(rho_bar, u_body), with
   //    rho_bar the mean lagged density of neighbours that were fluid at n.
-  //    (The paper is silent on this; parity unpinned.)
+  //    (The paper is silent on this.  The velocity is pinned by a body
+  //    carried along by a uniform flow; the density average is unpinned.)
   if (d.body.kind != 0) {
     for (long n = 0; n < N; ++n) {
       if (!(d.solid[n] && !solid_new[n])) continue;
@@ -578,7 +583,9 @@ void step_once(Domain& d) {
     //    is fluid; the wall velocity if neither is), averaged over the missing
     //    links.  Velocity gradient: finite differences of the lagged velocity,
     //    using the wall point on the cut side.  (Target-value formulas are a
-    //    reading of the paper's description; parity unpinned.)
+    //    reading of the paper's description, pinned by Couette at q != 1/2 and
+    //    by a body carried by a uniform flow, except the linear fallback and
+    //    the central-difference factor, which are unpinned.)
     if (any_missing && !inlet_node && !outlet_node) {
       const double* Ax = &d.A[n * Q];
       double rho_t = 0.0;
@@ -982,7 +989,8 @@ int orc_moments(void* h, double* rho, double* u, double* totals) {
 // sigma is sampled at x_q + n_q and x_q + 2 n_q, linearly extrapolated to the
 // surface, sigma_q = 2 sigma(p1) - sigma(p2); traction t_q = sigma_q n_q; the
 // force of the fluid on the body is F = sum_q w_q t_q.  The extrapolation
-// scheme is a reading of "similar to Kollmannsberger et al."; parity unpinned.
+// scheme is a reading of the paper's reference to an earlier scheme; it is
+// pinned by the exact wall traction of developed Poiseuille flow.
 // Arrays are point-major with D components (xq[q*D + a]).
 int orc_wall_force(void* h, const double* xq, const double* nq, const double* wq, int nqp,
                    double* traction, double* force) {

@@ -124,8 +124,57 @@ def test_poiseuille_channel_inlet_outlet_walls(orc):
         flux = (rho.reshape(ny, nx) * ux).sum(axis=0)[2:-2]
         assert (flux.max() - flux.min()) / flux.mean() < 5e-3
         assert np.max(np.abs(u[1].reshape(ny, nx)[:, H:-H])) < 1e-3 * ubar
+        if H == 16:
+            # Wall traction (Sec. II.C.2): the shear stress of the developed
+            # flow is linear across the channel, so the linear extrapolation
+            # of sigma from x_q + n_q and x_q + 2 n_q to the wall is exact.
+            # The tangential traction must equal the wall shear rho nu du/dy,
+            # 6 nu (mass flux) / H^2 for the parabola, on both walls, and the
+            # normal traction -p = -rho/3.  Sampling at x_q + n_q or
+            # x_q + 2 n_q alone, extrapolating the wrong way, or dropping the
+            # (1 - beta) factor of the viscous stress misses by 12% or more.
+            xs = np.arange(H, 3 * H).astype(float)
+            xq = np.concatenate([np.stack([xs, np.full_like(xs, -0.5)], 1),
+                                 np.stack([xs, np.full_like(xs, ny - 0.5)], 1)])
+            nq = np.concatenate([np.tile([0.0, 1.0], (xs.size, 1)),
+                                 np.tile([0.0, -1.0], (xs.size, 1))])
+            F, tr, st = d.wall_force(xq, nq, np.ones(xq.shape[0]))
+            assert st == 0
+            ix = np.concatenate([xs, xs]).astype(int)
+            r2 = rho.reshape(ny, nx)
+            fx = (r2 * ux).sum(axis=0)
+            tau = 6.0 * nu * fx[ix] / (H * H)
+            assert np.max(np.abs(tr[:, 0] / tau - 1.0)) < 1e-2
+            rw = np.concatenate([r2[0, ix[: xs.size]], r2[-1, ix[: xs.size]]])
+            assert np.max(np.abs(tr[:, 1] * nq[:, 1] / (-rw / 3.0) - 1.0)) < 1e-4
     assert errs[1] < 4e-3
     assert math.log2(errs[0] / errs[1]) > 1.5, errs
+
+
+def test_body_carried_by_uniform_flow_leaves_it_uniform(orc):
+    """A circle moving at the velocity U of the uniform flow around it
+    (Galilean co-motion): every target velocity is U, the velocity gradient
+    vanishes, and the fluid stays uniform up to the O(U^2) difference between
+    the entropic equilibrium and Grad's second-order reconstruction.  The
+    body moves four spacings, so nodes it uncovers are refilled every few
+    steps.  A refill at rest instead of at the body velocity, a wrong sign or
+    a dropped wall-motion term in the target density (Sec. II.C.1), or
+    interpolation weights that do not sum to one leave an O(U) defect."""
+    n, U, nu = 48, 0.02, 0.02
+    amp = 1.0e4   # sin(omega t) ~ omega t: the body velocity is U to 1e-7
+    d = orc.Domain(9, n, n, 1, nu)
+    N = n * n
+    u = np.zeros((2, N))
+    u[0] = U
+    d.init_fields(np.ones(N), u)
+    d.set_body(W.BODY_SPHERE, W.sphere_params((20.3, 24.1), 6.2, (amp, 0.0),
+                                              2.0 * math.pi * amp / U))
+    d.step(200)
+    rho, uu, tot = d.moments()
+    fl = d.solid() == 0
+    assert np.max(np.abs(uu[0][fl] - U)) < 5e-5 * U
+    assert np.max(np.abs(uu[1][fl])) < 5e-5 * U
+    assert np.max(np.abs(rho[fl] - 1.0)) < 2e-6
 
 
 def test_resting_sphere_is_fixed_point_and_force_free(orc):
