@@ -580,12 +580,17 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
 // ---------------------------------------------------------------------------
 // Boundary kernel: special nodes of the scanned regions.
 // ---------------------------------------------------------------------------
+// Coordinates of a box-local index (x fastest).  A box lies inside one
+// instance, so the index is below 2^31 and 32-bit division is exact (64-bit
+// division is a long software sequence on this target).
 __device__ __forceinline__ bool box_local(const Region& rg, int64_t local, int& x, int& y, int& z) {
-  const int64_t ex = rg.hi[0] - rg.lo[0], ey = rg.hi[1] - rg.lo[1];
-  x = rg.lo[0] + (int)(local % ex);
-  const int64_t r = local / ex;
-  y = rg.lo[1] + (int)(r % ey);
-  z = rg.lo[2] + (int)(r / ey);
+  const uint32_t ex = (uint32_t)(rg.hi[0] - rg.lo[0]), ey = (uint32_t)(rg.hi[1] - rg.lo[1]);
+  const uint32_t l = (uint32_t)local;
+  const uint32_t r = l / ex;
+  const uint32_t zz = r / ey;
+  x = rg.lo[0] + (int)(l - r * ex);
+  y = rg.lo[1] + (int)(r - zz * ey);
+  z = rg.lo[2] + (int)zz;
   return z < rg.hi[2];
 }
 
@@ -622,20 +627,30 @@ __global__ void __launch_bounds__(256) k_boundary_scan(const InstDev* __restrict
     take = owned && !(fv & FLAG_SOLID) && (fv & (FLAG_STATIC | FLAG_BODY));
     face = (x == 0 && I.face[0] == LBM_FACE_INLET) || (x == I.nx - 1 && I.face[1] == LBM_FACE_OUTLET);
   }
-  const int lane = threadIdx.x & 63;
+  // One atomic per list and workgroup (not per wave): every wave of a face
+  // plane has nodes to append, and same-address atomics serialise.
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ uint32_t s_cnt[2][4];
+  __shared__ uint32_t s_base[2];
+  uint64_t m[2];
 #pragma unroll
   for (int which = 0; which < 2; ++which) {
-    const bool mine = take && (face == (which == 1));
-    const uint64_t m = __ballot(mine);
-    if (m) {
-      const int leader = __ffsll((unsigned long long)m) - 1;
-      uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(count + which, (uint32_t)__popcll(m));
-      base = __shfl(base, leader);
-      if (mine) {
-        const uint32_t slot = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-        if (slot < cap) list[which * cap + slot] = make_uint2((uint32_t)rg.inst, node);
-      }
+    m[which] = __ballot(take && (face == (which == 1)));
+    if (lane == 0) s_cnt[which][wv] = (uint32_t)__popcll(m[which]);
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int which = threadIdx.x;
+    const uint32_t tot = s_cnt[which][0] + s_cnt[which][1] + s_cnt[which][2] + s_cnt[which][3];
+    s_base[which] = tot ? atomicAdd(count + which, tot) : 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int which = 0; which < 2; ++which) {
+    if (take && (face == (which == 1))) {
+      uint32_t slot = s_base[which] + (uint32_t)__popcll(m[which] & ((1ull << lane) - 1ull));
+      for (int w = 0; w < wv; ++w) slot += s_cnt[which][w];
+      if (slot < cap) list[which * cap + slot] = make_uint2((uint32_t)rg.inst, node);
     }
   }
 }
