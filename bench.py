@@ -307,28 +307,47 @@ def tg512_workload(lbm, torch, args):
             "forms": forms}
 
 
-def cpu_baseline(seconds=12.0):
-    """The oracle as it stands, on a bounded sample of the workload."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(seconds=12.0, one_thread_seconds=6.0):
+    """The oracle as it stands, on a bounded sample of the workload: all host
+    threads (the reported value), then one thread for reference."""
     import oracle
     import workloads as W
 
     n = 64
     rho, u, nu = W.taylor_green_3d(n)
-    d = oracle.Domain(27, n, n, n, nu)
-    d.init_fields(rho, u)
+
+    def run(threads, budget):
+        d = oracle.Domain(27, n, n, n, nu)
+        d.init_fields(rho, u)
+        d.set_threads(threads)
+        d.step(1)
+        steps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget:
+            d.step(1)
+            steps += 1
+        el = time.perf_counter() - t0
+        return n ** 3 * steps / el / 1e6, steps, el
+
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    d.set_threads(threads)
-    d.step(1)
-    steps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        d.step(2)
-        steps += 2
-    el = time.perf_counter() - t0
-    return {"value": n ** 3 * steps / el / 1e6, "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
+    v, steps, el = run(threads, seconds)
+    v1, steps1, el1 = run(1, one_thread_seconds)
+    return {"value": v, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": "D3Q27 KBC Taylor-Green 64^3 periodic (same Re, Ma, perturbation), "
-                      "FP64, %d steps in %.1f s" % (steps, el)}
+                      "FP64, %d steps in %.1f s" % (steps, el),
+            "one_thread": {"value": v1, "sample": "%d steps in %.1f s" % (steps1, el1)},
+            "cpu_model": _cpu_model()}
 
 
 def main():
