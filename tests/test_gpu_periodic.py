@@ -196,16 +196,22 @@ def test_tg3d_32_f32_1000_steps_within_tolerance():
     assert errs[1000] <= 1e-5
 
 
+@pytest.mark.parametrize("Q", [27, 9])
 @pytest.mark.parametrize("storage,mode", [("f16", "f16"), ("bf16", "bf16")])
-def test_16bit_storage_one_step_within_one_ulp(storage, mode):
-    n = 16
-    say("case: one step %s D3Q27 n=%d" % (storage, n))
-    rho, u, nu = W.taylor_green_3d(n, re=400.0, ma=0.1, perturb=1e-3, seed=6)
-    s = solver(Q=27, nx=n, ny=n, nz=n, nu=nu, storage=storage)
+def test_16bit_storage_one_step_within_one_ulp(storage, mode, Q):
+    n = 16 if Q == 27 else 40
+    say("case: one step %s Q=%d n=%d" % (storage, Q, n))
+    if Q == 27:
+        rho, u, nu = W.taylor_green_3d(n, re=400.0, ma=0.1, perturb=1e-3, seed=6)
+        nz = n
+    else:
+        rho, u = W.taylor_green_2d(n, 0.05)
+        nu, nz = 0.01, 1
+    s = solver(Q=Q, nx=n, ny=n, nz=nz, nu=nu, storage=storage)
     s.init_fields(rho, u)
-    d = oracle.Domain(27, n, n, n, nu, storage=mode)
+    d = oracle.Domain(Q, n, n, nz, nu, storage=mode)
     d.init_fields(rho, u)
-    w = lattice_w(27)[:, None]
+    w = lattice_w(Q)[:, None]
     g0, o0 = s.get_populations() - w, d.get_populations() - w
     s.step(1)
     d.step(1)
