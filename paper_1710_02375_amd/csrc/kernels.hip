@@ -657,8 +657,8 @@ __global__ void __launch_bounds__(256) k_boundary_scan(const InstDev* __restrict
 
 // Inflow / outflow plane nodes, one thread per node (Sec. III.A.1 inflow
 // with its ramp): equilibrium at the inflow velocity and the lagged density of
-// x + e_x, or at density 1 and the lagged velocity of x - e_x; then the
-// collision in FP64 like every boundary node.
+// x + e_x, or at density 1 and the lagged velocity of x - e_x, formed in FP64;
+// its collision is the identity (see below).
 template <int Q, int ST>
 __global__ void __launch_bounds__(64) k_boundary_face(StepBuffers b, const uint2* __restrict__ list,
                                                      const uint32_t* __restrict__ count,
