@@ -723,13 +723,40 @@ __global__ void __launch_bounds__(64) k_boundary_face(StepBuffers b, const uint2
   if (b.stats) block_stats<64>(gmin, gmax, gsum, cnt, f64, b.stats + stat0 + blockIdx.x);
 }
 
-// Sum over the GL lanes of a group (GL a power of two <= 64), same value in
-// every lane of the group, fixed order.
+// One DPP lane exchange of a double (two 32-bit moves); CTRL is the DPP
+// control word: 0xB1 / 0x4E swap neighbours / pairs within a quad, 0x141
+// mirrors each 8-lane half-row, 0x140 each 16-lane row.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum over the GL lanes of a group (GL = 32 or 64; all 64 lanes active), the
+// same value in every lane of the group, fixed order.  Register-to-register
+// DPP exchanges within each 16-lane row (every step adds the same pair in
+// both lanes, so the row sum is identical across the row), then the row sums
+// are read back as scalars: no LDS round trips.
 template <int GL>
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int o = GL / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  static_assert(GL == 32 || GL == 64, "group of 32 or 64 lanes");
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x141>(v);
+  v += dpp_f64<0x140>(v);
+  const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16);
+  const double r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
+  if (GL == 64) return (r0 + r1) + (r2 + r3);
+  return (threadIdx.x & 32) ? r2 + r3 : r0 + r1;
 }
 
 // Value for lattice velocity component c in {0, +1, -1}; the operands are
