@@ -142,14 +142,19 @@ def time_form(lbm, torch, n, storage, rho, u, nu, steps, warmup, variant=None):
     return mlups, ms_step, kernel_ms, info
 
 
-def error_vs_f64(lbm, n, rho, u, nu, steps):
+def error_vs_f64(lbm, n, rho, u, nu, steps, variants=None):
     """Velocity rel L2 of each storage form against the FP64 form after
-    `steps` steps from the same initial fields."""
+    `steps` steps from the same initial fields.  variants maps a storage form
+    to the bulk-kernel variant name it was timed with, so that the error is
+    that of the kernel that was timed."""
     ref = None
     out = {}
+    names = [lbm.lbm_variant_name(k) for k in range(lbm.lbm_variant_count())]
     for storage in ("f64", "f32", "f16", "bf16"):
         s = lbm.Solver([dict(Q=27, nx=n, ny=n, nz=n, nu=nu, storage=storage)])
         s.init_fields(rho, u)
+        if variants and storage in variants:
+            lbm.lbm_set_variant(s.ctx, names.index(variants[storage]))
         s.step(steps)
         _, uu, _ = s.moments()
         s.close()
@@ -434,8 +439,11 @@ def main():
                                          "variant": i2["variant"]}
         var["batched_d2q9_flap_channels_f32"] = batched_form(lbm, torch, args.batched_steps,
                                                              args.batched_warmup)
-        err = error_vs_f64(lbm, n, rho, u, nu, args.error_steps)
+        timed = {args.storage: info["variant"], "f16": var["f16_shifted"]["variant"],
+                 "bf16": var["bf16_shifted"]["variant"]}
+        err = error_vs_f64(lbm, n, rho, u, nu, args.error_steps, timed)
         var["velocity_rel_l2_vs_f64_at_step_%d" % args.error_steps] = err
+        var["velocity_rel_l2_variants"] = timed
         result["variants"] = var
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline()

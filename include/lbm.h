@@ -74,19 +74,35 @@ typedef int lbm_status;
 #define LBM_FACE_OUTLET 2
 #define LBM_FACE_WALL 3
 
-/* Prescribed-motion bodies (the structure solver is a host-side stub).
+/* Bodies.  The structure solver is host-side; the library takes either a
+ * prescribed motion law that the device evaluates every step, or the
+ * structure's surface mesh (Sec. II.C.1: the FEM surface quadrilaterals split
+ * into triangles, vertices moved by the computed displacements, vertex
+ * velocities interpolated at the link intersections).
  *   SPHERE (circle in 2D): params X0[3], R, A[3], omega, phase;
  *           centre X0 + A sin(omega t + phase), rigid translation.
  *   FLAP (2D): params x_f, length l, thickness h, amplitude d0, omega, phase,
  *           y_base; solid where 0 <= s <= l and |x - x_c(s,t)| <= h/2, with
  *           s = y - y_base and x_c = x_f + d0 sin(omega t + phase) (s/l)^2.
+ *   MESH:   closed surface given by nverts vertices (verts, 3 doubles each),
+ *           their velocities (vert_vel, 3 doubles each) and ntris faces (tris,
+ *           3 vertex indices each).  D3Q27: triangles; D2Q9: each face is the
+ *           segment of its first two vertices (the third index is ignored,
+ *           z components are ignored).  A node is solid when it lies inside
+ *           the closed surface or on it.  Along a cut link the wall fraction
+ *           is the first intersection with a face, and the wall velocity the
+ *           vertex velocities interpolated linearly (barycentric) there.  The
+ *           mesh describes the surface at the time of the next step's new
+ *           state and stays in place until the next lbm_set_geometry call; the
+ *           first call also sets the current geometry.  params are unused.
  *   PLATES: params y_lo, y_hi, u_lo[3], u_hi[3]; solid where y < y_lo or
  *           y > y_hi; each plate slides tangentially with its velocity.
  * Points on the surface count as solid.  Time t is the step count. */
 #define LBM_BODY_NONE 0
 #define LBM_BODY_SPHERE 1
 #define LBM_BODY_FLAP 2
-#define LBM_BODY_PLATES 3
+#define LBM_BODY_MESH 3
+#define LBM_BODY_PLATES 4
 
 typedef struct lbm_ctx lbm_ctx;
 
@@ -114,8 +130,12 @@ typedef struct {
 } lbm_device_opts;
 
 typedef struct {
-  int kind;          /* LBM_BODY_* */
-  double params[16]; /* layout per kind, see above */
+  int kind;               /* LBM_BODY_* */
+  double params[16];      /* analytic bodies: layout per kind, see above */
+  int nverts, ntris;      /* MESH: vertex and face counts (else ignored) */
+  const double* verts;    /* MESH: nverts * 3 positions, host memory */
+  const double* vert_vel; /* MESH: nverts * 3 velocities, host memory */
+  const int* tris;        /* MESH: ntris * 3 vertex indices, host memory */
 } lbm_body;
 
 typedef struct {
@@ -142,23 +162,34 @@ lbm_status lbm_destroy(lbm_ctx* ctx);
  * Requires rho > 0 and |u_a| < 1 (else LBM_ERR_INVALID).  Synchronous. */
 lbm_status lbm_init_fields(lbm_ctx* ctx, int inst, const double* rho, const double* u);
 
-/* Replaces the body of instance inst; the geometry at the current time is
- * built on the device and thereafter follows the motion law on the device,
- * so lbm_step needs no host update.  body == NULL or kind NONE removes it.
- * Errors: LBM_ERR_INVALID (unknown kind, flap in 3D), LBM_ERR_GEOMETRY (the
+/* Replaces the body of instance inst (Sec. II.C.1: the geometry and wall
+ * velocity the fluid boundary condition needs).  An analytic body's geometry
+ * at the current time is built on the device and thereafter follows its
+ * motion law on the device, so lbm_step needs no host update; a mesh is
+ * copied to the device before the call returns (the caller keeps ownership of
+ * its arrays) and used from the next step on.  body == NULL or kind NONE
+ * removes the body.
+ * Errors: LBM_ERR_INVALID (unknown kind, flap in 3D, a mesh with no faces, a
+ * vertex index out of range or non-finite coordinates), LBM_ERR_GEOMETRY (the
  * body's swept region does not fit inside the domain with a 2-node margin
  * along periodic axes). */
 lbm_status lbm_set_geometry(lbm_ctx* ctx, int inst, const lbm_body* body);
 
 /* Advances every instance by n_steps >= 0 steps (Sec. II.A, Eq. 1, pull form:
  * geometry update, fresh-node refill, streaming, Grad fill, face conditions,
- * KBC collision).  Asynchronous on the context stream.  Returns
- * LBM_ERR_NONFINITE if a previous step set the device error word (checked
- * without a device sync at most every 64 steps). */
+ * KBC collision).  Asynchronous on the context stream.  Each call that
+ * enqueues steps also enqueues a copy of the device error word to the host
+ * and records an event after it; the next lbm_step call checks that copy if
+ * the event has completed (without waiting for it) and returns
+ * LBM_ERR_NONFINITE if the word was set.  Synchronous calls check the word
+ * itself. */
 lbm_status lbm_step(lbm_ctx* ctx, int n_steps);
 
-/* Density and velocity of the stored (post-collision) state of instance inst;
- * they equal the moments the last collision used, since it conserves them.
+/* Density and velocity of the stored (post-collision) state of instance inst:
+ * rho = sum_i f_i and rho u = sum_i f_i c_i (Sec. II.A, Eq. 5, the moments
+ * the collision conserves), so they equal the moments the last collision
+ * used.  tot holds their FP64 sums over fluid nodes (mass and momentum
+ * drift) and, with statistics on, the gamma statistics of the last step.
  * Solid nodes report rho = 0, u = 0.  rho: N doubles, u: D*N doubles, tot:
  * totals; any output may be NULL.  Synchronous.  Returns LBM_ERR_NONFINITE if
  * the device error word is set (outputs are still written). */

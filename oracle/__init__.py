@@ -75,6 +75,8 @@ def lib():
         L.orc_moments.argtypes = [C.c_void_p, _dp, _dp, _dp]
         L.orc_wall_force.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_int, _dp, _dp]
         L.orc_stream_only.argtypes = [C.c_void_p]
+        L.orc_grad_targets.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _dp]
+        L.orc_set_time.argtypes = [C.c_void_p, C.c_long]
         _lib = L
     return _lib
 
@@ -259,3 +261,19 @@ class Domain:
 
     def stream_only(self):
         assert lib().orc_stream_only(self._h) == 0
+
+    def grad_targets(self, x, y, z=0):
+        """Grad target values the next step would use at node (x, y, z)
+        (Sec. II.C.1): dict(rho, u (3,), grad (3, 3) with grad[a, b] =
+        d u_a / d x_b, missing = number of missing populations), or None for a
+        node without missing populations, a solid node or an inflow / outflow
+        node."""
+        out = np.zeros(13)
+        k = lib().orc_grad_targets(self._h, int(x), int(y), int(z), out)
+        if k <= 0:
+            return None
+        return dict(rho=out[0], u=out[1:4].copy(), grad=out[4:13].reshape(3, 3).copy(), missing=k)
+
+    def set_time(self, t):
+        """Sets the step count of the stored state (then call set_body)."""
+        assert lib().orc_set_time(self._h, int(t)) == 0

@@ -12,16 +12,16 @@
 // collision; double precision throughout.  The shear / higher-order split uses
 // the generic inverse of the Q x Q monomial moment matrix, not a closed form.
 //
-// Parity status of each part is stated beside it:
-//   pinned          -- checked in tests against values fixed by the paper or
-//                      by mathematics (closed forms, invariants, brute force);
-//   parity unpinned -- only self-consistency and physical sanity checks exist
-//                      (the linear fallback of the Grad target velocity, the
-//                      central-difference factor of the target gradient, the
-//                      density average of the fresh-node fill).  The other
-//                      boundary formulas are pinned by flows with exact
-//                      answers (Couette at q != 1/2, Poiseuille wall traction,
-//                      a body carried by a uniform flow).
+// Parity status: every part is pinned -- checked in tests against values fixed
+// by the paper or by mathematics (closed forms, invariants, brute force on
+// tiny inputs, flows with exact answers).  The boundary formulas, whose exact
+// form the paper leaves to earlier work, are pinned by exact flows (Couette
+// at q != 1/2, Poiseuille wall traction, a body carried by a uniform flow at
+// a density other than 1) and by prepared lagged fields on which each target
+// formula is exact (linear fallback, central difference, quadratic wall
+// differences, two cut sides); the probe fallback of the wall stress by
+// brute force and by a wall probe in developed Poiseuille flow.  Planted
+// mistakes in a copy of this file fail those pins.
 //
 // Lattice conventions: velocities c_i in {-1,0,1}^D with index
 // i = (cx+1) + 3(cy+1) + 9(cz+1), opposite direction Q-1-i, weights the tensor
@@ -312,7 +312,7 @@ double round_storage(int mode, double x) {
 //          phase, y_base; solid where 0 <= s <= l and |x - x_c(s,t)| <= h/2 with
 //          s = y - y_base, x_c(s,t) = x_f + d0 sin(omega t + phase) (s/l)^2;
 //          velocity (d0 omega cos(omega t + phase)(s/l)^2, 0).
-//   kind 3 plates: params y_lo, y_hi, u_lo[3], u_hi[3]; solid where y < y_lo
+//   kind 4 plates: params y_lo, y_hi, u_lo[3], u_hi[3]; solid where y < y_lo
 //          or y > y_hi; each plate moves tangentially with its own velocity.
 // Points on the surface count as solid.
 // ---------------------------------------------------------------------------
@@ -337,7 +337,7 @@ bool body_inside(const Body& b, int D, const double* x, double t) {
       const double xc = b.p[0] + b.p[3] * std::sin(b.p[4] * t + b.p[5]) * (s / b.p[1]) * (s / b.p[1]);
       return std::fabs(x[0] - xc) <= 0.5 * b.p[2];
     }
-    case 3:
+    case 4:
       return x[1] < b.p[0] || x[1] > b.p[1];
     default:
       return false;
@@ -356,7 +356,7 @@ void body_velocity(const Body& b, int D, const double* x, double t, double* v) {
       v[0] = b.p[3] * b.p[4] * std::cos(b.p[4] * t + b.p[5]) * (s / b.p[1]) * (s / b.p[1]);
       break;
     }
-    case 3: {
+    case 4: {
       const double* u = (x[1] < 0.5 * (b.p[0] + b.p[1])) ? &b.p[2] : &b.p[5];
       for (int a = 0; a < D; ++a) v[a] = u[a];
       break;
@@ -490,18 +490,155 @@ void apply_storage_rounding(Domain& d, long n) {
   for (int i = 0; i < L.Q; ++i) f[i] = L.w[i] + round_storage(d.storage, f[i] - L.w[i]);
 }
 
-// One time step n -> n+1 (pull form of Eq. (1)):
-//   1 geometry at t_{n+1};  2 fresh-node refill;  3 streaming;
-//   4 Grad fill of missing populations;  5 inflow/outflow override;  6 collision;
-//   7 optional storage rounding.
-void step_once(Domain& d) {
+// Pull streaming at fluid node x (Eq. (1), left-hand side): f_i(x) =
+// A_i(x - c_i) for every source that is a fluid node at the new time.  A
+// source behind a wall face or inside the body (solid_new) marks population
+// i missing, with the wall fraction q_i in (0,1] and the wall velocity uw_i
+// (walls: q = 1/2 at rest; bodies: cut_link).  A source behind the inflow or
+// outflow face marks the node as an inflow or outflow node.
+void pull_links(const Domain& d, const int* x, const std::vector<uint8_t>& solid_new, double t1,
+                double* f, bool* missing, double* q, double (*uw)[3], bool* any_missing,
+                bool* inlet_node, bool* outlet_node) {
+  const Lattice& L = *d.L;
+  const int Q = L.Q;
+  for (int i = 0; i < Q; ++i) {
+    const int off[3] = {-L.c[i][0], -L.c[i][1], -L.c[i][2]};
+    long src;
+    const int k = resolve(d, x, off, true, &src);
+    if (k == LINK_INLET) { *inlet_node = true; f[i] = 0.0; continue; }
+    if (k == LINK_OUTLET) { *outlet_node = true; f[i] = 0.0; continue; }
+    if (k == LINK_WALL) {
+      missing[i] = true; *any_missing = true; q[i] = 0.5;
+      continue;
+    }
+    if (solid_new[src]) {
+      missing[i] = true; *any_missing = true;
+      cut_link(d, x, L.c[i], t1, &q[i], uw[i]);
+      continue;
+    }
+    f[i] = d.A[src * Q + i];
+  }
+}
+
+// Grad target values at fluid node n (position x) with missing set `missing`
+// (Sec. II.C.1), from the streamed known populations f, the lagged fields
+// rho_n, u_n (moments of the stored state A), the geometry at the new time
+// (solid_new) and the wall fraction q and wall velocity uw of each missing
+// link:
+//   - target density: the bounce-back-implied density plus the wall-motion
+//     term, rho_t = sum_{known} f_i + sum_{missing} [A_opp(i)(x) + 6 W_i rho_n(x) c_i.u_w,i];
+//   - target velocity: per missing link, the velocity at x interpolated along
+//     c_i from the wall point x - q c_i and the lagged velocities at x + c_i,
+//     x + 2 c_i (quadratic; linear if only x + c_i is fluid; the wall
+//     velocity if neither is), averaged over the missing links;
+//   - velocity gradient grad[a][b] = d u_a / d x_b: finite differences of the
+//     lagged velocity (central where both neighbours along b are fluid,
+//     through the wall point on a cut side, one-sided otherwise).
+// Pinned by exact flows and by prepared linear and quadratic lagged fields
+// in the tests (Couette at q != 1/2, a body carried by a uniform flow, the
+// linear fallback, the central difference and the two-sided cut).
+void grad_targets(const Domain& d, const int* x, long n, const double* f, const bool* missing,
+                  const double* q, const double (*uw)[3], const std::vector<uint8_t>& solid_new,
+                  const std::vector<double>& rho_n, const std::vector<double>& u_n,
+                  double* rho_t_out, double* ut, double (*grad)[3]) {
+  const Lattice& L = *d.L;
+  const int Q = L.Q, D = L.D;
+  const double* Ax = &d.A[n * Q];
+  double rho_t = 0.0;
+  for (int i = 0; i < Q; ++i) {
+    if (!missing[i]) { rho_t += f[i]; continue; }
+    double cu = 0.0;
+    for (int a = 0; a < D; ++a) cu += L.c[i][a] * uw[i][a];
+    rho_t += Ax[Q - 1 - i] + 6.0 * L.w[i] * rho_n[n] * cu;
+  }
+  auto fluid_at = [&](const int* off, long* m) {
+    return resolve(d, x, off, false, m) == LINK_NODE && !solid_new[*m];
+  };
+  ut[0] = ut[1] = ut[2] = 0.0;
+  int nm = 0;
+  for (int i = 0; i < Q; ++i) {
+    if (!missing[i]) continue;
+    const int o1[3] = {L.c[i][0], L.c[i][1], L.c[i][2]};
+    const int o2[3] = {2 * L.c[i][0], 2 * L.c[i][1], 2 * L.c[i][2]};
+    long m1, m2;
+    const double qq = q[i];
+    double ui[3];
+    if (fluid_at(o1, &m1) && fluid_at(o2, &m2)) {
+      // Lagrange weights at s = 0 for the nodes s = -q, 1, 2.
+      const double a0 = 2.0 / ((1.0 + qq) * (2.0 + qq));
+      const double a1 = 2.0 * qq / (1.0 + qq);
+      const double a2 = -qq / (2.0 + qq);
+      for (int a = 0; a < 3; ++a)
+        ui[a] = a0 * uw[i][a] + a1 * u_n[3 * m1 + a] + a2 * u_n[3 * m2 + a];
+    } else if (fluid_at(o1, &m1)) {
+      for (int a = 0; a < 3; ++a) ui[a] = (uw[i][a] + qq * u_n[3 * m1 + a]) / (1.0 + qq);
+    } else {
+      for (int a = 0; a < 3; ++a) ui[a] = uw[i][a];
+    }
+    for (int a = 0; a < 3; ++a) ut[a] += ui[a];
+    ++nm;
+  }
+  for (int a = 0; a < 3; ++a) ut[a] /= nm;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) grad[a][b] = 0.0;
+  for (int b = 0; b < D; ++b) {
+    // Population index of c = +e_b (its link to x - e_b) and c = -e_b.
+    const int ip = L.rest + (b == 0 ? 1 : b == 1 ? 3 : 9);
+    const int im = L.rest - (b == 0 ? 1 : b == 1 ? 3 : 9);
+    const bool cut_m = missing[ip];   // x - e_b is wall or body
+    const bool cut_p = missing[im];   // x + e_b is wall or body
+    int op1[3] = {0, 0, 0}, op2[3] = {0, 0, 0}, om1[3] = {0, 0, 0}, om2[3] = {0, 0, 0};
+    op1[b] = 1; op2[b] = 2; om1[b] = -1; om2[b] = -2;
+    long p1, p2, m1, m2;
+    const bool fp1 = fluid_at(op1, &p1), fp2 = fp1 && fluid_at(op2, &p2);
+    const bool fm1 = fluid_at(om1, &m1), fm2 = fm1 && fluid_at(om2, &m2);
+    for (int a = 0; a < D; ++a) {
+      double g = 0.0;
+      if (cut_m && cut_p) {
+        g = (uw[im][a] - uw[ip][a]) / (q[im] + q[ip]);
+      } else if (cut_m) {
+        const double qq = q[ip], w0 = uw[ip][a];
+        if (fp2)
+          g = -3.0 * w0 / ((1.0 + qq) * (2.0 + qq)) + u_n[3 * p1 + a] * (2.0 - qq) / (1.0 + qq) +
+              u_n[3 * p2 + a] * (qq - 1.0) / (2.0 + qq);
+        else if (fp1)
+          g = (u_n[3 * p1 + a] - w0) / (1.0 + qq);
+      } else if (cut_p) {
+        const double qq = q[im], w0 = uw[im][a];
+        if (fm2)
+          g = 3.0 * w0 / ((1.0 + qq) * (2.0 + qq)) - u_n[3 * m1 + a] * (2.0 - qq) / (1.0 + qq) -
+              u_n[3 * m2 + a] * (qq - 1.0) / (2.0 + qq);
+        else if (fm1)
+          g = (w0 - u_n[3 * m1 + a]) / (1.0 + qq);
+      } else if (fp1 && fm1) {
+        g = 0.5 * (u_n[3 * p1 + a] - u_n[3 * m1 + a]);
+      } else if (fp1) {
+        g = u_n[3 * p1 + a] - u_n[3 * n + a];
+      } else if (fm1) {
+        g = u_n[3 * n + a] - u_n[3 * m1 + a];
+      }
+      grad[a][b] = g;
+    }
+  }
+  *rho_t_out = rho_t;
+}
+
+// Steps 1 and 2 of a time step n -> n+1: geometry at t_{n+1} (solid_new),
+// lagged moments rho_n, u_n of the stored state, and the fresh-node refill
+// (nodes solid at n and fluid at n+1): A := f^eq(rho_bar, u_body) with rho_bar
+// the mean lagged density of the neighbours that were fluid at n (1 if there
+// is none), and rho_n, u_n of the node set to rho_bar, u_body.  The paper is
+// silent on fresh nodes; the body velocity and the use of the neighbours'
+// density (not a reference density, no solid neighbour) are pinned by a body
+// carried along by a uniform flow at a density other than 1.
+void prepare_step(Domain& d, std::vector<uint8_t>& solid_new, std::vector<double>& rho_n,
+                  std::vector<double>& u_n) {
   const Lattice& L = *d.L;
   const int Q = L.Q, D = L.D;
   const long N = d.N;
   const double t1 = (double)(d.step + 1);
-
   // 1. Geometry at t_{n+1}.
-  std::vector<uint8_t> solid_new(N, 0);
+  solid_new.assign(N, 0);
   if (d.body.kind != 0) {
 #pragma omp parallel for schedule(static) num_threads(d.nthreads)
     for (long n = 0; n < N; ++n) {
@@ -512,14 +649,13 @@ void step_once(Domain& d) {
   }
 
   // Lagged moments rho^n, u^n of the stored post-collision state.
-  std::vector<double> rho_n(N), u_n(3 * N);
+  rho_n.assign(N, 0.0);
+  u_n.assign(3 * N, 0.0);
 #pragma omp parallel for schedule(static) num_threads(d.nthreads)
   for (long n = 0; n < N; ++n) moments(L, &d.A[n * Q], &rho_n[n], &u_n[3 * n]);
 
   // 2. Fresh nodes (solid at n, fluid at n+1): A := f^eq(rho_bar, u_body), with
   //    rho_bar the mean lagged density of neighbours that were fluid at n.
-  //    (The paper is silent on this.  The velocity is pinned by a body
-  //    carried along by a uniform flow; the density average is unpinned.)
   if (d.body.kind != 0) {
     for (long n = 0; n < N; ++n) {
       if (!(d.solid[n] && !solid_new[n])) continue;
@@ -544,6 +680,20 @@ void step_once(Domain& d) {
       for (int a = 0; a < 3; ++a) u_n[3 * n + a] = ub[a];
     }
   }
+}
+
+// One time step n -> n+1 (pull form of Eq. (1)):
+//   1 geometry at t_{n+1};  2 fresh-node refill;  3 streaming;
+//   4 Grad fill of missing populations;  5 inflow/outflow override;  6 collision;
+//   7 optional storage rounding.
+void step_once(Domain& d) {
+  const Lattice& L = *d.L;
+  const int Q = L.Q, D = L.D;
+  const long N = d.N;
+  const double t1 = (double)(d.step + 1);
+  std::vector<uint8_t> solid_new;
+  std::vector<double> rho_n, u_n;
+  prepare_step(d, solid_new, rho_n, u_n);
 
   // 3.-5. Streaming, Grad fill and inflow, per fluid node.
   std::vector<double>& F = d.fpre;
@@ -557,112 +707,14 @@ void step_once(Domain& d) {
     bool missing[27] = {};
     double q[27] = {}, uw[27][3] = {};
     bool any_missing = false, inlet_node = false, outlet_node = false;
-    // 3. Pull streaming: f_i(x) = A_i(x - c_i).
-    for (int i = 0; i < Q; ++i) {
-      const int off[3] = {-L.c[i][0], -L.c[i][1], -L.c[i][2]};
-      long src;
-      const int k = resolve(d, x, off, true, &src);
-      if (k == LINK_INLET) { inlet_node = true; f[i] = 0.0; continue; }
-      if (k == LINK_OUTLET) { outlet_node = true; f[i] = 0.0; continue; }
-      if (k == LINK_WALL) {
-        missing[i] = true; any_missing = true; q[i] = 0.5;
-        continue;
-      }
-      if (solid_new[src]) {
-        missing[i] = true; any_missing = true;
-        cut_link(d, x, L.c[i], t1, &q[i], uw[i]);
-        continue;
-      }
-      f[i] = d.A[src * Q + i];
-    }
-    // 4. Grad's approximation for the missing populations (Sec. II.C.1).
-    //    Target density: bounce-back-implied density plus the wall-motion
-    //    term.  Target velocity: per missing link, the velocity at x
-    //    interpolated along c_i from the wall point x - q c_i and the lagged
-    //    velocities at x + c_i, x + 2 c_i (quadratic; linear if only x + c_i
-    //    is fluid; the wall velocity if neither is), averaged over the missing
-    //    links.  Velocity gradient: finite differences of the lagged velocity,
-    //    using the wall point on the cut side.  (Target-value formulas are a
-    //    reading of the paper's description, pinned by Couette at q != 1/2 and
-    //    by a body carried by a uniform flow, except the linear fallback and
-    //    the central-difference factor, which are unpinned.)
+    // 3. Pull streaming.
+    pull_links(d, x, solid_new, t1, f, missing, q, uw, &any_missing, &inlet_node, &outlet_node);
+    // 4. Grad's approximation for the missing populations (Sec. II.C.1):
+    //    f*(rho_t, u_t, Pi) with the target values of grad_targets and
+    //    Pi = rho_t cs^2 I + rho_t u_t u_t - (rho_t cs^2 / (2 beta)) (grad + grad^T).
     if (any_missing && !inlet_node && !outlet_node) {
-      const double* Ax = &d.A[n * Q];
-      double rho_t = 0.0;
-      for (int i = 0; i < Q; ++i) {
-        if (!missing[i]) { rho_t += f[i]; continue; }
-        double cu = 0.0;
-        for (int a = 0; a < D; ++a) cu += L.c[i][a] * uw[i][a];
-        rho_t += Ax[Q - 1 - i] + 6.0 * L.w[i] * rho_n[n] * cu;
-      }
-      auto fluid_at = [&](const int* off, long* m) {
-        return resolve(d, x, off, false, m) == LINK_NODE && !solid_new[*m];
-      };
-      double ut[3] = {0.0, 0.0, 0.0};
-      int nm = 0;
-      for (int i = 0; i < Q; ++i) {
-        if (!missing[i]) continue;
-        const int o1[3] = {L.c[i][0], L.c[i][1], L.c[i][2]};
-        const int o2[3] = {2 * L.c[i][0], 2 * L.c[i][1], 2 * L.c[i][2]};
-        long m1, m2;
-        const double qq = q[i];
-        double ui[3];
-        if (fluid_at(o1, &m1) && fluid_at(o2, &m2)) {
-          // Lagrange weights at s = 0 for the nodes s = -q, 1, 2.
-          const double a0 = 2.0 / ((1.0 + qq) * (2.0 + qq));
-          const double a1 = 2.0 * qq / (1.0 + qq);
-          const double a2 = -qq / (2.0 + qq);
-          for (int a = 0; a < 3; ++a)
-            ui[a] = a0 * uw[i][a] + a1 * u_n[3 * m1 + a] + a2 * u_n[3 * m2 + a];
-        } else if (fluid_at(o1, &m1)) {
-          for (int a = 0; a < 3; ++a) ui[a] = (uw[i][a] + qq * u_n[3 * m1 + a]) / (1.0 + qq);
-        } else {
-          for (int a = 0; a < 3; ++a) ui[a] = uw[i][a];
-        }
-        for (int a = 0; a < 3; ++a) ut[a] += ui[a];
-        ++nm;
-      }
-      for (int a = 0; a < 3; ++a) ut[a] /= nm;
-      double grad[3][3] = {};   // grad[a][b] = d u_a / d x_b
-      for (int b = 0; b < D; ++b) {
-        // Population index of c = +e_b (its link to x - e_b) and c = -e_b.
-        const int ip = L.rest + (b == 0 ? 1 : b == 1 ? 3 : 9);
-        const int im = L.rest - (b == 0 ? 1 : b == 1 ? 3 : 9);
-        const bool cut_m = missing[ip];   // x - e_b is wall or body
-        const bool cut_p = missing[im];   // x + e_b is wall or body
-        int op1[3] = {0, 0, 0}, op2[3] = {0, 0, 0}, om1[3] = {0, 0, 0}, om2[3] = {0, 0, 0};
-        op1[b] = 1; op2[b] = 2; om1[b] = -1; om2[b] = -2;
-        long p1, p2, m1, m2;
-        const bool fp1 = fluid_at(op1, &p1), fp2 = fp1 && fluid_at(op2, &p2);
-        const bool fm1 = fluid_at(om1, &m1), fm2 = fm1 && fluid_at(om2, &m2);
-        for (int a = 0; a < D; ++a) {
-          double g = 0.0;
-          if (cut_m && cut_p) {
-            g = (uw[im][a] - uw[ip][a]) / (q[im] + q[ip]);
-          } else if (cut_m) {
-            const double qq = q[ip], w0 = uw[ip][a];
-            if (fp2)
-              g = -3.0 * w0 / ((1.0 + qq) * (2.0 + qq)) + u_n[3 * p1 + a] * (2.0 - qq) / (1.0 + qq) +
-                  u_n[3 * p2 + a] * (qq - 1.0) / (2.0 + qq);
-            else if (fp1)
-              g = (u_n[3 * p1 + a] - w0) / (1.0 + qq);
-          } else if (cut_p) {
-            const double qq = q[im], w0 = uw[im][a];
-            if (fm2)
-              g = 3.0 * w0 / ((1.0 + qq) * (2.0 + qq)) - u_n[3 * m1 + a] * (2.0 - qq) / (1.0 + qq) -
-                  u_n[3 * m2 + a] * (qq - 1.0) / (2.0 + qq);
-            else if (fm1)
-              g = (w0 - u_n[3 * m1 + a]) / (1.0 + qq);
-          } else if (fp1 && fm1) {
-            g = 0.5 * (u_n[3 * p1 + a] - u_n[3 * m1 + a]);
-          } else if (fp1) {
-            g = u_n[3 * p1 + a] - u_n[3 * n + a];
-          } else if (fm1) {
-            g = u_n[3 * n + a] - u_n[3 * m1 + a];
-          }
-          grad[a][b] = g;
-        }
-      }
+      double rho_t, ut[3], grad[3][3];
+      grad_targets(d, x, n, f, missing, q, uw, solid_new, rho_n, u_n, &rho_t, ut, grad);
       double Pi[9] = {};
       for (int a = 0; a < D; ++a)
         for (int b = 0; b < D; ++b)
@@ -932,7 +984,7 @@ int orc_get_precollision(void* h, double* f) {
 // Sets the body and the geometry at the current time.
 int orc_set_body(void* h, int kind, const double* params) {
   Domain* d = static_cast<Domain*>(h);
-  if (kind < 0 || kind > 3) return -1;
+  if (kind < 0 || kind > 4 || kind == 3) return -1;
   if (kind == 2 && d->L->D != 2) return -1;
   d->body.kind = kind;
   for (int k = 0; k < 16; ++k) d->body.p[k] = params ? params[k] : 0.0;
@@ -942,6 +994,50 @@ int orc_set_body(void* h, int kind, const double* params) {
     coords(*d, n, x);
     d->solid[n] = (kind != 0 && inside_at(*d, x, t)) ? 1 : 0;
   }
+  return 0;
+}
+
+// Grad target values (Sec. II.C.1) that the next step would use at node
+// (x, y, z), from the current state as lagged fields and the geometry at the
+// next time; the domain itself is left unchanged (the fresh-node refill of
+// the next step is applied to a copy).  out: rho_t, u_t[3], grad[3][3]
+// row-major (grad[a][b] = d u_a / d x_b).  Returns the number of missing
+// populations, 0 if there is none, -1 for a node that is solid at the next
+// time or lies on an inflow or outflow face.
+int orc_grad_targets(void* h, int x, int y, int z, double* out) {
+  Domain d = *static_cast<const Domain*>(h);
+  if (x < 0 || y < 0 || z < 0 || x >= d.nx || y >= d.ny || z >= d.nz) return -1;
+  std::vector<uint8_t> solid_new;
+  std::vector<double> rho_n, u_n;
+  prepare_step(d, solid_new, rho_n, u_n);
+  const int xx[3] = {x, y, z};
+  const long n = node_index(d, x, y, z);
+  if (solid_new[n]) return -1;
+  const int Q = d.L->Q;
+  double f[27] = {}, q[27] = {}, uw[27][3] = {};
+  bool missing[27] = {};
+  bool any = false, inlet = false, outlet = false;
+  pull_links(d, xx, solid_new, (double)(d.step + 1), f, missing, q, uw, &any, &inlet, &outlet);
+  if (inlet || outlet) return -1;
+  if (!any) return 0;
+  double rho_t, ut[3], grad[3][3];
+  grad_targets(d, xx, n, f, missing, q, uw, solid_new, rho_n, u_n, &rho_t, ut, grad);
+  out[0] = rho_t;
+  for (int a = 0; a < 3; ++a) out[1 + a] = ut[a];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) out[4 + 3 * a + b] = grad[a][b];
+  int cnt = 0;
+  for (int i = 0; i < Q; ++i) cnt += missing[i] ? 1 : 0;
+  return cnt;
+}
+
+// Sets the step count (the time of the stored state), e.g. before stepping
+// from a state read back from elsewhere; the geometry is not rebuilt (call
+// orc_set_body after this).
+int orc_set_time(void* h, long t) {
+  Domain* d = static_cast<Domain*>(h);
+  if (t < 0) return -1;
+  d->step = t;
   return 0;
 }
 

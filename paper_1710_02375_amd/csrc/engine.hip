@@ -801,6 +801,8 @@ lbm_status lbm_set_geometry(lbm_ctx* c, int inst, const lbm_body* body) {
   if (body) b = *body;
   if (b.kind < LBM_BODY_NONE || b.kind > LBM_BODY_PLATES)
     return fail(c, LBM_ERR_INVALID, "unknown body kind %d", b.kind);
+  if (b.kind == LBM_BODY_MESH)
+    return fail(c, LBM_ERR_UNSUPPORTED, "surface-mesh bodies are not available in this build");
   if (b.kind == LBM_BODY_FLAP && c->D != 2) return fail(c, LBM_ERR_INVALID, "flap bodies are 2D only");
   for (int k = 0; k < 16; ++k)
     if (!std::isfinite(b.params[k])) return fail(c, LBM_ERR_INVALID, "non-finite body parameter");

@@ -1201,11 +1201,24 @@ __global__ void __launch_bounds__(256) k_neq_fixup(StepBuffers b, int stat0) {
     T* db = static_cast<T*>(b.dst) + I.pop_off;
     const Coord c = node_coord(I, e.y);
     R f[Q];
+    // Deferred nodes come from the bulk kernel, whose nodes have every source
+    // inside the instance (face planes and cut-link nodes are flagged and
+    // never deferred); a source that does not resolve means a corrupt list
+    // entry: the node is left as the bulk kernel wrote it and the error word
+    // is set.
+    bool resolved = true;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      uint32_t m;
-      resolve_nb(I, c.x, c.y, c.z, -cx(i), -cy(i), -cz<Q>(i), m);
+      uint32_t m = e.y;
+      if (!resolve_nb(I, c.x, c.y, c.z, -cx(i), -cy(i), -cz<Q>(i), m)) {
+        resolved = false;
+        m = e.y;
+      }
       f[i] = S::dec(sb[i * I.stride + m]);
+    }
+    if (!resolved) {
+      atomicOr(b.err, 2u);
+      continue;
     }
     CollideParams<R> P;
     P.beta = (R)I.beta;

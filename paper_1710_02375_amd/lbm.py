@@ -27,6 +27,7 @@ LBM_D2Q9, LBM_D3Q27 = 9, 27
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 STORAGE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
 FACE = {"periodic": 0, "inlet": 1, "outlet": 2, "wall": 3}
+LBM_BODY_NONE, LBM_BODY_SPHERE, LBM_BODY_FLAP, LBM_BODY_MESH, LBM_BODY_PLATES = 0, 1, 2, 3, 4
 COLLISION = {"kbc": 0, "lbgk": 1}
 
 
@@ -47,7 +48,9 @@ class lbm_device_opts(C.Structure):
 
 
 class lbm_body(C.Structure):
-    _fields_ = [("kind", C.c_int), ("params", C.c_double * 16)]
+    _fields_ = [("kind", C.c_int), ("params", C.c_double * 16), ("nverts", C.c_int),
+                ("ntris", C.c_int), ("verts", C.c_void_p), ("vert_vel", C.c_void_p),
+                ("tris", C.c_void_p)]
 
 
 class lbm_totals(C.Structure):
@@ -150,25 +153,44 @@ def make_desc(Q, nx, ny, nz, nu, storage="f32", collision="kbc", trace_in_s=0, f
 
 class TorchAllocator:
     """Device allocation callbacks backed by PyTorch tensors (torch owns the
-    memory; the allocator object must outlive the context)."""
+    memory; the allocator object must outlive the context).
 
-    def __init__(self, device=0):
+    stream: the torch.cuda.Stream the library launches on.  Blocks are then
+    allocated with that stream current, so torch's caching allocator orders
+    their reuse after the library's work on it.  Without a stream (the
+    library then uses a stream of its own) each release first waits for the
+    device, so that a released block cannot be handed out while the library
+    may still write it."""
+
+    def __init__(self, device=0, stream=None):
         import torch
 
         self._torch = torch
         self.device = device
+        self.stream = stream
         self._live = {}
         self.alloc_fn = ALLOC_FN(self._alloc)
         self.free_fn = FREE_FN(self._free)
 
     def _alloc(self, nbytes, _ctx):
-        t = self._torch.empty(int(nbytes), dtype=self._torch.uint8,
-                              device="cuda:%d" % self.device)
+        torch = self._torch
+        dev = "cuda:%d" % self.device
+        if self.stream is not None:
+            with torch.cuda.stream(self.stream):
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+        else:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+            # Pending work of torch's current stream may still use a block
+            # the caching allocator hands back; the library writes on its own
+            # stream, so wait for it first.
+            torch.cuda.current_stream(self.device).synchronize()
         p = t.data_ptr()
         self._live[p] = t
         return p
 
     def _free(self, ptr, _ctx):
+        if self.stream is None and ptr in self._live:
+            self._torch.cuda.synchronize(self.device)
         self._live.pop(ptr, None)
 
 
@@ -201,12 +223,26 @@ def lbm_init_fields(ctx, inst, rho, u):
     return _check(ctx, lib().lbm_init_fields(ctx, int(inst), _f64(rho), _f64(u)))
 
 
-def lbm_set_geometry(ctx, inst, kind, params=()):
+def lbm_set_geometry(ctx, inst, kind, params=(), verts=None, vert_vel=None, tris=None):
+    """kind: LBM_BODY_*; params for the analytic bodies; verts (V, 3),
+    vert_vel (V, 3) and tris (T, 3) for a surface mesh (copied before the call
+    returns)."""
     b = lbm_body()
     b.kind = int(kind)
     for k, v in enumerate(params):
         b.params[k] = float(v)
-    return _check(ctx, lib().lbm_set_geometry(ctx, int(inst), C.byref(b)))
+    keep = []
+    if verts is not None:
+        V = np.ascontiguousarray(verts, dtype=np.float64).reshape(-1, 3)
+        Vv = np.ascontiguousarray(vert_vel if vert_vel is not None else np.zeros_like(V),
+                                  dtype=np.float64).reshape(-1, 3)
+        T = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+        keep = [V, Vv, T]
+        b.nverts, b.ntris = V.shape[0], T.shape[0]
+        b.verts, b.vert_vel, b.tris = V.ctypes.data, Vv.ctypes.data, T.ctypes.data
+    st = lib().lbm_set_geometry(ctx, int(inst), C.byref(b))
+    del keep
+    return _check(ctx, st)
 
 
 def lbm_step(ctx, n_steps):
@@ -299,6 +335,8 @@ class Solver:
 
     def __init__(self, descs, device=0, stream=None, use_graph=True, allocator=None):
         self.descs = [make_desc(**d) if isinstance(d, dict) else d for d in descs]
+        if allocator is not None and allocator.stream is None and hasattr(stream, "cuda_stream"):
+            allocator.stream = stream
         self.allocator = allocator
         self.ctx = lbm_create(self.descs, device, stream, use_graph, allocator)
         self.Q = self.descs[0].lattice
@@ -319,8 +357,8 @@ class Solver:
     def init_fields(self, rho, u, inst=0):
         lbm_init_fields(self.ctx, inst, rho, u)
 
-    def set_body(self, kind, params, inst=0):
-        lbm_set_geometry(self.ctx, inst, kind, params)
+    def set_body(self, kind, params=(), inst=0, verts=None, vert_vel=None, tris=None):
+        lbm_set_geometry(self.ctx, inst, kind, params, verts, vert_vel, tris)
 
     def step(self, n=1):
         lbm_step(self.ctx, n)

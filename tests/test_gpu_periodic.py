@@ -113,13 +113,27 @@ def test_one_step_f32(Q):
     assert ratio < 1e-6
 
 
+def storage_ulp(mode, o, w):
+    """Storage ulp of each (shifted) oracle value, floored at the FP32
+    arithmetic bound 1e-6 W_i (deviations near zero have a tiny BF16/FP16
+    ulp, below what FP32 arithmetic resolves)."""
+    p = 11 if mode == "f16" else 8
+    emin = -14 if mode == "f16" else -126
+    e = np.maximum(np.floor(np.log2(np.maximum(np.abs(o), 1e-300))), emin)
+    return np.maximum(2.0 ** (e - p + 1), 1e-6 * w)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "f64"])
 @pytest.mark.parametrize("Q,dims", [(27, (19, 13, 11)), (9, (37, 23, 1))])
-def test_every_bulk_variant_on_ragged_dims(Q, dims):
+def test_every_bulk_variant_on_ragged_dims(Q, dims, storage):
     """Odd sizes: no dimension a power of two, and the node count a multiple
     neither of the 64-lane wavefront nor of any tile, so every variant ends on
     a partial tile and the coordinate division meets odd divisors.  Each bulk
-    variant takes one FP32 step that must match the oracle; variants differ
-    only in launch shape and addressing, so they must also agree bitwise."""
+    variant takes one step in each storage form that must match the oracle
+    (FP64: to 1e-13; FP32: |df| <= 1e-6 W_i; FP16/BF16 against the oracle
+    that rounds to the same format: one storage ulp on 99.9% of entries, two
+    at most); variants differ only in launch shape and addressing, so they
+    must also agree bitwise."""
     from paper_1710_02375_amd import lbm
 
     nx, ny, nz = dims
@@ -128,28 +142,82 @@ def test_every_bulk_variant_on_ragged_dims(Q, dims):
     rng = np.random.default_rng(2375)
     rho = 1.0 + 0.02 * rng.standard_normal(N)
     u = 0.05 * rng.standard_normal((D, N))
-    say("case: every bulk variant, F32 Q=%d dims=%s N=%d" % (Q, dims, N))
-    d = oracle.Domain(Q, nx, ny, nz, 0.02)
+    say("case: every bulk variant, %s Q=%d dims=%s N=%d" % (storage, Q, dims, N))
+    mode = storage if storage in ("f16", "bf16") else "f64"
+    d = oracle.Domain(Q, nx, ny, nz, 0.02, storage=mode)
     d.init_fields(rho, u)
     d.step(1)
-    ref = d.get_populations()
     w = lattice_w(Q)[:, None]
+    ref = d.get_populations()
     outs = []
     worst = 0.0
     for v in range(lbm.lbm_variant_count()):
-        s = solver(Q=Q, nx=nx, ny=ny, nz=nz, nu=0.02, storage="f32")
+        s = solver(Q=Q, nx=nx, ny=ny, nz=nz, nu=0.02, storage=storage)
         s.init_fields(rho, u)
         lbm.lbm_set_variant(s.ctx, v)
         s.step(1)
         f = s.get_populations()
         s.close()
-        ratio = float(np.max(np.abs(f - ref) / w))
-        worst = max(worst, ratio)
-        assert ratio < 1e-6, lbm.lbm_variant_name(v)
+        name = lbm.lbm_variant_name(v)
+        if storage == "f64":
+            err = float(np.max(np.abs(f - ref)))
+            assert err < 1e-13, name
+        elif storage == "f32":
+            err = float(np.max(np.abs(f - ref) / w))
+            assert err < 1e-6, name
+        else:
+            k = np.abs((f - w) - (ref - w)) / storage_ulp(mode, ref - w, w)
+            err = float(k.max())
+            assert np.mean(k <= 1.0 + 1e-9) >= 0.999, name
+            assert err <= 2.0 + 1e-9, name
+        worst = max(worst, err)
         outs.append(f)
-    say("  %d variants, worst one-step max |df| / W_i = %.3e" % (len(outs), worst))
+    say("  %d variants, worst one-step difference %.3e (%s)"
+        % (len(outs), worst, {"f64": "abs", "f32": "/W_i"}.get(storage, "storage ulp")))
     for v, f in enumerate(outs[1:], 1):
         assert np.array_equal(f, outs[0]), lbm.lbm_variant_name(v)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_fp64_gamma_pass_runs_and_matches_oracle(storage, monkeypatch):
+    """The deferred FP64-gamma pass (Sec. II.A, Eq. 6, evaluated in FP64 for
+    nodes FP32 cannot resolve) is forced onto every node by a relative
+    threshold far above any node's <Delta|Delta>: the statistics must report
+    it on (nearly) every node, and every population must still agree with the
+    oracle, after one step and after 20 graph-replayed steps."""
+    from paper_1710_02375_amd import lbm
+
+    monkeypatch.setenv("KBC_NEAR_EQ", "1e30")
+    n = 14
+    say("case: forced FP64 gamma pass, %s D3Q27 n=%d" % (storage, n))
+    rho, u, nu = W.taylor_green_3d(n, re=300.0, ma=0.15, perturb=0.02, seed=11)
+    mode = storage if storage == "f16" else "f64"
+    s = lbm.Solver([dict(Q=27, nx=n, ny=n, nz=n, nu=nu, storage=storage)])
+    s.set_stats(True)
+    s.init_fields(rho, u)
+    d = oracle.Domain(27, n, n, n, nu, storage=mode)
+    d.init_fields(rho, u)
+    w = lattice_w(27)[:, None]
+    for steps in (1, 20):
+        s.step(steps)
+        d.step(steps)
+        _, ug, tot = s.moments()
+        f, ref = s.get_populations(), d.get_populations()
+        if storage == "f32":
+            err = float(np.max(np.abs(f - ref) / w))
+            say("  after %d steps: fp64 share %.4f, max |df|/W_i %.3e"
+                % (d.time, tot["fp64_gamma_fraction"], err))
+            assert err < (1e-6 if steps == 1 else 2e-5)
+        else:
+            k = np.abs((f - w) - (ref - w)) / storage_ulp(mode, ref - w, w)
+            say("  after %d steps: fp64 share %.4f, max %.1f storage ulp"
+                % (d.time, tot["fp64_gamma_fraction"], k.max()))
+            if steps == 1:
+                assert np.mean(k <= 1.0 + 1e-9) >= 0.999 and k.max() <= 2.0 + 1e-9
+        assert tot["fp64_gamma_fraction"] > 0.99
+    _, uo, _ = d.moments()
+    assert np.linalg.norm(ug - uo) / np.linalg.norm(uo) < (1e-5 if storage == "f32" else 5e-3)
+    s.close()
 
 
 def test_cfg1_tg2d_64_f64_analytic_and_oracle():
@@ -216,11 +284,7 @@ def test_16bit_storage_one_step_within_one_ulp(storage, mode, Q):
     s.step(1)
     d.step(1)
     g, o = s.get_populations() - w, d.get_populations() - w
-    # storage ulp of each oracle value
-    p = 11 if mode == "f16" else 8
-    emin = -14 if mode == "f16" else -126
-    e = np.maximum(np.floor(np.log2(np.maximum(np.abs(o), 1e-300))), emin)
-    ulp = np.maximum(2.0 ** (e - p + 1), 1e-6 * w)
+    ulp = storage_ulp(mode, o, w)
     k = np.abs(g - o) / ulp
     frac1 = np.mean(k <= 1.0 + 1e-9)
     say("  init max ulp diff %.1f; step 1: max %.1f ulp, share within 1 ulp %.5f"
@@ -391,9 +455,12 @@ def test_gamma_statistics_and_torch_allocator():
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 def test_16bit_storage_error_vs_fp64_oracle(storage):
     """D3Q27 TG 32^3 at Re=1600: velocity error of the 16-bit shifted forms
-    against the FP64 oracle after 200 and 1000 steps.  FP16 is gated at 5e-3
-    after 200 steps; BF16 and the 1000-step values are recorded with loose
-    bounds (storage rounding dominates and accumulates)."""
+    against the FP64 oracle after 200 and 1000 steps, stated per result.
+    FP16 meets the 5e-3 target at step 200 (measured ~4e-4) and misses it at
+    step 1000 (measured 5.6e-3 to 5.8e-3: storage rounding of the deviations,
+    2^-11 relative, accumulates); that point is gated at 6.5e-3, just above
+    the measured value, so a regression shows.  BF16 (2^-8 relative) is
+    reported with the bounds its rounding allows (measured ~4e-3 and ~5e-2)."""
     n = 32
     say("case: D3Q27 TG 32^3 %s vs FP64 oracle" % storage)
     rho, u, nu = W.taylor_green_3d(n)
@@ -411,7 +478,7 @@ def test_16bit_storage_error_vs_fp64_oracle(storage):
     say("  %s velocity rel L2: step 200 %.3e, step 1000 %.3e" % (storage, errs[200], errs[1000]))
     if storage == "f16":
         assert errs[200] <= 5e-3
-        assert errs[1000] <= 2e-2
+        assert errs[1000] <= 6.5e-3
     else:
-        assert errs[200] <= 2e-2
-        assert errs[1000] <= 1e-1
+        assert errs[200] <= 1e-2
+        assert errs[1000] <= 8e-2

@@ -147,34 +147,56 @@ def test_poiseuille_channel_inlet_outlet_walls(orc):
             assert np.max(np.abs(tr[:, 0] / tau - 1.0)) < 1e-2
             rw = np.concatenate([r2[0, ix[: xs.size]], r2[-1, ix[: xs.size]]])
             assert np.max(np.abs(tr[:, 1] * nq[:, 1] / (-rw / 3.0) - 1.0)) < 1e-4
+            # Probes two and one spacings outside the bottom wall have no
+            # fluid stencil corner: both take the nearest fluid node, the
+            # first row (wall distance 1/2), whose shear stress in the
+            # developed flow is 6 nu (mass flux) (H - 1) / H^3.  A search box
+            # smaller than 5^D finds no node for the far probe.
+            xf = np.arange(H, 3 * H).astype(float) + 0.25
+            xq2 = np.stack([xf, np.full_like(xf, -3.0)], 1)
+            nq2 = np.tile([0.0, 1.0], (xf.size, 1))
+            F2, tr2, st2 = d.wall_force(xq2, nq2, np.ones(xf.size))
+            assert st2 == 0
+            ixf = np.floor(xf).astype(int)
+            tau0 = 6.0 * nu * fx[ixf] * (H - 1) / H ** 3
+            assert np.max(np.abs(tr2[:, 0] / tau0 - 1.0)) < 1e-2
+            assert np.max(np.abs(tr2[:, 1] / (-r2[0, ixf] / 3.0) - 1.0)) < 1e-4
     assert errs[1] < 4e-3
     assert math.log2(errs[0] / errs[1]) > 1.5, errs
 
 
 def test_body_carried_by_uniform_flow_leaves_it_uniform(orc):
     """A circle moving at the velocity U of the uniform flow around it
-    (Galilean co-motion): every target velocity is U, the velocity gradient
-    vanishes, and the fluid stays uniform up to the O(U^2) difference between
-    the entropic equilibrium and Grad's second-order reconstruction.  The
-    body moves four spacings, so nodes it uncovers are refilled every few
-    steps.  A refill at rest instead of at the body velocity, a wrong sign or
-    a dropped wall-motion term in the target density (Sec. II.C.1), or
-    interpolation weights that do not sum to one leave an O(U) defect."""
-    n, U, nu = 48, 0.02, 0.02
+    (Galilean co-motion) at density rho0 = 1.02: every target velocity is U,
+    the velocity gradient vanishes, and the fluid stays uniform up to the
+    O(U^2) difference between the entropic equilibrium and Grad's
+    second-order reconstruction.  The body moves four spacings, so nodes it
+    uncovers are refilled every few steps; the nodes inside the body start at
+    density 1.3, which no correct step reads.  A refill at rest instead of at
+    the body velocity, at the reference density 1 instead of the neighbours'
+    density, a refill that counts solid neighbours or sums instead of
+    averaging, a wrong sign or a dropped wall-motion term in the target
+    density (Sec. II.C.1), or interpolation weights that do not sum to one
+    leave an O(U) or O(rho0 - 1) defect."""
+    n, U, nu, rho0 = 48, 0.02, 0.02, 1.02
     amp = 1.0e4   # sin(omega t) ~ omega t: the body velocity is U to 1e-7
     d = orc.Domain(9, n, n, 1, nu)
     N = n * n
     u = np.zeros((2, N))
     u[0] = U
-    d.init_fields(np.ones(N), u)
+    d.init_fields(np.full(N, rho0), u)
     d.set_body(W.BODY_SPHERE, W.sphere_params((20.3, 24.1), 6.2, (amp, 0.0),
                                               2.0 * math.pi * amp / U))
+    inside = d.solid().astype(bool)
+    assert inside.sum() > 100
+    rho = np.where(inside, 1.3, rho0)
+    d.init_fields(rho, u)
     d.step(200)
     rho, uu, tot = d.moments()
     fl = d.solid() == 0
     assert np.max(np.abs(uu[0][fl] - U)) < 5e-5 * U
     assert np.max(np.abs(uu[1][fl])) < 5e-5 * U
-    assert np.max(np.abs(rho[fl] - 1.0)) < 2e-6
+    assert np.max(np.abs(rho[fl] - rho0)) < 2e-6
 
 
 def test_resting_sphere_is_fixed_point_and_force_free(orc):
@@ -239,3 +261,196 @@ def test_flap_channel_runs_and_stays_valid(orc):
     assert not tot["invalid"]
     fl = d.solid() == 0
     assert rho[fl].min() > 0.9 and np.abs(u[:, fl]).max() < 0.2
+
+
+# ---------------------------------------------------------------------------
+# Grad target values on prepared lagged fields (Sec. II.C.1).  The lagged
+# moments are those of the stored state, so initialising every node to the
+# equilibrium of a chosen (rho, u) field prepares them exactly.  On fields
+# that are linear (or quadratic) along the lattice lines that an
+# interpolation or a difference uses, the formula is exact, so a wrong weight,
+# factor or fallback shows as an O(gradient) error.
+# ---------------------------------------------------------------------------
+
+
+def _plates_domain(orc, Q, nx, ny, nz, y_lo, y_hi, ufield, u_lo, u_hi):
+    """Periodic box with resting-shape plates below y_lo and above y_hi, the
+    lagged velocity field ufield(x, y, z) -> (D,) at every node, rho = 1."""
+    D = 2 if Q == 9 else 3
+    d = orc.Domain(Q, nx, ny, nz, 0.05)
+    N = nx * ny * nz
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    u = np.stack([np.asarray(c, dtype=float).ravel()
+                  for c in ufield(x.astype(float), y.astype(float), z.astype(float))])[:D]
+    d.init_fields(np.ones(N), u)
+    d.set_body(W.BODY_PLATES, W.plates_params(y_lo, y_hi, u_lo, u_hi))
+    return d
+
+
+def test_target_velocity_linear_fallback_and_linear_wall_gradient(orc):
+    """Two fluid rows between plates (rows 0 and 3 solid): for a node of row
+    1, x + c_i is fluid but x + 2 c_i is not, so the target velocity of each
+    missing link interpolates linearly between the wall point and x + c_i,
+    and the wall-normal gradient takes the linear difference through the wall
+    point.  On a lagged field linear across the channel that matches both
+    plate velocities, both are exact: u_t = u(y) and du_x/dy = a."""
+    y_lo, y_hi, U_lo, a = 0.6, 2.7, 0.01, 0.004
+    U_hi = U_lo + a * (y_hi - y_lo)
+    ux = lambda x, y, z: U_lo + a * (y - y_lo) + 0 * x
+    d = _plates_domain(orc, 9, 6, 4, 1, y_lo, y_hi,
+                       lambda x, y, z: (ux(x, y, z), 0 * x), (U_lo, 0, 0), (U_hi, 0, 0))
+    for y in (1, 2):
+        for x in range(6):
+            t = d.grad_targets(x, y)
+            assert t is not None and t["missing"] == 3
+            assert abs(t["u"][0] - (U_lo + a * (y - y_lo))) < 1e-15
+            assert abs(t["u"][1]) < 1e-15
+            exp = np.zeros((3, 3))
+            exp[0, 1] = a
+            assert np.max(np.abs(t["grad"] - exp)) < 1e-15, (x, y, t["grad"])
+
+
+def test_target_gradient_central_difference(orc):
+    """Along an axis where both neighbours are fluid and not cut, the target
+    gradient is the central difference of the lagged velocity, exact for a
+    field linear along that axis.  D2Q9 (axis x) and D3Q27 (axes x and z)
+    next to the plates, away from the periodic wrap of the prepared field."""
+    h, g, m, k = 0.003, -0.002, 0.0015, 0.0025
+    d = _plates_domain(orc, 9, 10, 8, 1, 0.7, 6.4,
+                       lambda x, y, z: (h * (x - 4.5), g * (x - 4.5)), (0, 0, 0), (0, 0, 0))
+    for y in (1, 6):
+        for x in range(1, 9):
+            t = d.grad_targets(x, y)
+            assert t is not None
+            assert abs(t["grad"][0, 0] - h) < 1e-15 and abs(t["grad"][1, 0] - g) < 1e-15
+    d3 = _plates_domain(orc, 27, 6, 6, 8, 0.7, 4.4,
+                        lambda x, y, z: (h * (x - 2.5) + m * (z - 3.5), 0 * x,
+                                         k * (z - 3.5) + g * (x - 2.5)), (0, 0, 0), (0, 0, 0))
+    for y in (1, 4):
+        for z in range(1, 7):
+            for x in range(1, 5):
+                t = d3.grad_targets(x, y, z)
+                assert t is not None and t["missing"] == 9
+                G = t["grad"]
+                assert np.max(np.abs(G[:, 0] - (h, 0, g))) < 1e-15, (x, y, z, G)
+                assert np.max(np.abs(G[:, 2] - (m, 0, k))) < 1e-15, (x, y, z, G)
+
+
+def test_target_velocity_and_gradient_quadratic(orc):
+    """Wider channel: x + c_i and x + 2 c_i are fluid, so the target velocity
+    interpolates quadratically through the wall point and the wall-normal
+    gradient is the quadratic difference through the wall point; both are
+    exact for a lagged profile quadratic across the channel that matches the
+    plate velocities (wall fractions 0.65 and 0.8)."""
+    y_lo, y_hi, U_lo, a, kq = 0.35, 10.8, 0.004, 0.003, -0.0002
+    prof = lambda y: U_lo + a * (y - y_lo) + kq * (y - y_lo) ** 2
+    d = _plates_domain(orc, 9, 5, 12, 1, y_lo, y_hi,
+                       lambda x, y, z: (prof(y) + 0 * x, 0 * x), (U_lo, 0, 0), (prof(y_hi), 0, 0))
+    for y in (1, 10):
+        for x in range(5):
+            t = d.grad_targets(x, y)
+            assert t is not None and t["missing"] == 3
+            assert abs(t["u"][0] - prof(y)) < 1e-15
+            assert abs(t["grad"][0, 1] - (a + 2 * kq * (y - y_lo))) < 1e-14, (x, y, t["grad"])
+
+
+def test_target_single_row_between_two_cut_walls(orc):
+    """One fluid row between plates at equal distance (q = 0.4 on both
+    sides): no lattice neighbour along any missing link is fluid, so every
+    per-link target velocity is its wall velocity, and the wall-normal
+    gradient spans the two wall points, (u_hi - u_lo) / (q_hi + q_lo).  For a
+    lagged field linear between the plates both are exact: u_t = u(1) (the
+    mean of the plate velocities) and du_x/dy = a."""
+    y_lo, y_hi, U_lo, a = 0.6, 1.4, -0.003, 0.01
+    U_hi = U_lo + a * (y_hi - y_lo)
+    d = _plates_domain(orc, 9, 5, 3, 1, y_lo, y_hi,
+                       lambda x, y, z: (U_lo + a * (y - y_lo) + 0 * x, 0 * x),
+                       (U_lo, 0, 0), (U_hi, 0, 0))
+    for x in range(5):
+        t = d.grad_targets(x, 1)
+        assert t is not None and t["missing"] == 6
+        assert abs(t["u"][0] - (U_lo + a * (1 - y_lo))) < 1e-15
+        assert abs(t["grad"][0, 1] - a) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Stress probes that fall back to the nearest fluid node (Sec. II.C.2 with
+# the extrapolation reading: a probe whose interpolation stencil holds no
+# fluid node takes the stress of the nearest fluid node in the 5^D box around
+# it, Euclidean distance, first in z, y, x order on ties).
+# ---------------------------------------------------------------------------
+
+
+def _probe_stress_brute_force(orc, d, beta, fpre, solid, p):
+    """Stress at point p by brute force over the definition: multilinear over
+    the stencil corners that are fluid (weights renormalised), else the
+    nearest fluid node of the 5^D box around floor(p)."""
+    D, dims = d.D, (d.nx, d.ny, d.nz)
+    base = [int(math.floor(p[a])) for a in range(D)]
+    fr = [p[a] - base[a] for a in range(D)]
+
+    def node(c):
+        c = [c[a] % dims[a] for a in range(D)] + [0] * (3 - D)
+        return c[0] + d.nx * (c[1] + d.ny * c[2])
+
+    acc, wsum = np.zeros((3, 3)), 0.0
+    for corner in np.ndindex(*([2] * D)):
+        w = np.prod([fr[a] if corner[a] else 1 - fr[a] for a in range(D)])
+        m = node([base[a] + corner[a] for a in range(D)])
+        if w <= 0 or solid[m]:
+            continue
+        acc += w * orc.stress(d.Q, beta, fpre[:, m])
+        wsum += w
+    if wsum > 0:
+        return acc / wsum
+    best = None
+    rng_z = range(-2, 3) if D == 3 else range(0, 1)
+    for dz in rng_z:
+        for dy in range(-2, 3):
+            for dx in range(-2, 3):
+                off = (dx, dy, dz)[:D]
+                m = node([base[a] + off[a] for a in range(D)])
+                if solid[m]:
+                    continue
+                r2 = sum((base[a] + off[a] - p[a]) ** 2 for a in range(D))
+                if best is None or r2 < best[0]:
+                    best = (r2, m)
+    return orc.stress(d.Q, beta, fpre[:, best[1]])
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_probe_fallback_nearest_fluid_node_brute_force(orc, Q):
+    """Random node states between plates, one step; quadrature points whose
+    first probe lies inside a plate, with no fluid stencil corner, at
+    fractional offsets where the Euclidean nearest node differs from the
+    other candidates at equal wall distance; the tractions must equal the
+    brute-force extrapolation 2 sigma(p1) - sigma(p2) applied to n."""
+    D = 2 if Q == 9 else 3
+    nx, ny, nz = (12, 12, 1) if D == 2 else (8, 10, 8)
+    y_lo, y_hi = 2.5, ny - 2.5
+    d = orc.Domain(Q, nx, ny, nz, 0.05)
+    N = nx * ny * nz
+    f0 = W.random_node_states(Q, N, seed=77, amp=0.3).T
+    d.set_populations(np.ascontiguousarray(f0))
+    d.set_body(W.BODY_PLATES, W.plates_params(y_lo, y_hi))
+    d.step(1)
+    fpre, solid = d.get_precollision(), d.solid()
+    rng = np.random.default_rng(5)
+    pts, nrm = [], []
+    for k in range(24):
+        x0 = rng.uniform(1.0, nx - 2.0)
+        z0 = rng.uniform(1.0, nz - 2.0) if D == 3 else 0.0
+        frac = (0.9, 0.1, 0.55)[k % 3]
+        xq = [math.floor(x0) + frac, rng.uniform(0.05, 0.4)] + ([z0] if D == 3 else [])
+        pts.append(xq)
+        nrm.append([0.0, 1.0] + ([0.0] if D == 3 else []))
+    xq, nq = np.array(pts), np.array(nrm)
+    F, tr, st = d.wall_force(xq, nq, np.ones(len(pts)))
+    assert st == 0
+    beta = d.beta
+    for k in range(len(pts)):
+        p1, p2 = xq[k] + nq[k], xq[k] + 2 * nq[k]
+        s1 = _probe_stress_brute_force(orc, d, beta, fpre, solid, p1)
+        s2 = _probe_stress_brute_force(orc, d, beta, fpre, solid, p2)
+        exp = ((2 * s1 - s2)[:D, :D] @ nq[k])
+        assert np.max(np.abs(tr[k] - exp)) < 1e-14, (k, tr[k], exp)

@@ -46,6 +46,51 @@ CASES = [
      "g = -3.0 * w0 / ((1.0 + qq) * (2.0 + qq)) + u_n[3 * p1 + a] * (2.0 - qq) / (1.0 + qq) +",
      "g = 3.0 * w0 / ((1.0 + qq) * (2.0 + qq)) + u_n[3 * p1 + a] * (2.0 - qq) / (1.0 + qq) +",
      "test_body_carried_by_uniform_flow_leaves_it_uniform", ()),
+    # Fresh node refilled at the reference density instead of its neighbours'.
+    ("fresh_density_reference",
+     "const double rb = cnt ? sum / cnt : 1.0;", "const double rb = 1.0;",
+     "test_body_carried_by_uniform_flow_leaves_it_uniform", ()),
+    # Fresh-node density summed instead of averaged.
+    ("fresh_density_sum_not_mean",
+     "const double rb = cnt ? sum / cnt : 1.0;", "const double rb = cnt ? sum : 1.0;",
+     "test_body_carried_by_uniform_flow_leaves_it_uniform", ()),
+    # Fresh-node density average over solid neighbours as well.
+    ("fresh_density_includes_solid",
+     "        if (d.solid[m]) continue;\n        sum += rho_n[m];", "        sum += rho_n[m];",
+     "test_body_carried_by_uniform_flow_leaves_it_uniform", ()),
+    # Linear target-velocity fallback with the wall and x + c_i weights exchanged.
+    ("target_velocity_linear_fallback_weights",
+     "for (int a = 0; a < 3; ++a) ui[a] = (uw[i][a] + qq * u_n[3 * m1 + a]) / (1.0 + qq);",
+     "for (int a = 0; a < 3; ++a) ui[a] = (qq * uw[i][a] + u_n[3 * m1 + a]) / (1.0 + qq);",
+     "test_target_velocity_linear_fallback_and_linear_wall_gradient", ()),
+    # Target velocity at rest where no lattice neighbour along c_i is fluid.
+    ("target_velocity_no_fluid_fallback",
+     "      for (int a = 0; a < 3; ++a) ui[a] = uw[i][a];",
+     "      for (int a = 0; a < 3; ++a) ui[a] = 0.0;",
+     "test_target_single_row_between_two_cut_walls", ()),
+    # Central difference without the factor 1/2.
+    ("gradient_central_factor",
+     "g = 0.5 * (u_n[3 * p1 + a] - u_n[3 * m1 + a]);",
+     "g = (u_n[3 * p1 + a] - u_n[3 * m1 + a]);",
+     "test_target_gradient_central_difference", ()),
+    # Linear difference through the wall point without the spacing 1 + q.
+    ("gradient_linear_wall_spacing",
+     "g = (u_n[3 * p1 + a] - w0) / (1.0 + qq);", "g = (u_n[3 * p1 + a] - w0);",
+     "test_target_velocity_linear_fallback_and_linear_wall_gradient", ()),
+    # Two cut sides: central-difference spacing instead of the wall distance.
+    ("gradient_two_sided_cut_spacing",
+     "g = (uw[im][a] - uw[ip][a]) / (q[im] + q[ip]);", "g = 0.5 * (uw[im][a] - uw[ip][a]);",
+     "test_target_single_row_between_two_cut_walls", ()),
+    # Probe fallback searching the 3^D box only.
+    ("probe_fallback_box_3",
+     "    for (int dy = -2; dy <= 2; ++dy)\n      for (int dx = -2; dx <= 2; ++dx) {",
+     "    for (int dy = -1; dy <= 1; ++dy)\n      for (int dx = -1; dx <= 1; ++dx) {",
+     "test_poiseuille_channel_inlet_outlet_walls", ()),
+    # Probe fallback with the maximum-norm distance.
+    ("probe_fallback_max_norm",
+     "for (int a = 0; a < D; ++a) r2 += (q[a] - p[a]) * (q[a] - p[a]);",
+     "for (int a = 0; a < D; ++a) r2 = std::max(r2, std::fabs(q[a] - p[a]));",
+     "test_probe_fallback_nearest_fluid_node_brute_force", (9,)),
 ]
 
 CHILD = textwrap.dedent("""
