@@ -42,6 +42,8 @@ struct lbm_ctx {
   std::vector<int> moving;        // body moves (geometry changes every step)
   std::vector<char> has_body;
   std::vector<char> force_valid;
+  double* force_ws = nullptr;     // wall-force workspace, grown on demand
+  size_t force_ws_doubles = 0;
   int64_t total_nodes = 0;
   size_t pop_elems = 0;           // elements per population buffer
 
@@ -582,6 +584,7 @@ lbm_status lbm_destroy(lbm_ctx* c) {
   dev_free(c, c->dbtiles);
   dev_free(c, c->dgtiles);
   dev_free(c, c->dstats);
+  dev_free(c, c->force_ws);
   if (c->herr) (void)hipHostFree(c->herr);
   if (c->err_event) (void)hipEventDestroy(c->err_event);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -957,24 +960,29 @@ lbm_status lbm_moments(lbm_ctx* c, int inst, double* rho, double* u, lbm_totals*
   return check_error_word(c);
 }
 
-lbm_status lbm_wall_force(lbm_ctx* c, int inst, const double* xq, const double* nq,
-                          const double* wq, int n_q, double* traction, double force[3]) {
-  lbm_status st = check_inst(c, inst);
-  if (st) return st;
-  if (!force || n_q < 0 || (n_q > 0 && (!xq || !nq || !wq)))
-    return fail(c, LBM_ERR_INVALID, "bad quadrature arguments");
-  if (!c->force_valid[inst])
-    return fail(c, LBM_ERR_INVALID, "wall force needs a step after the last geometry or state change");
-  force[0] = force[1] = force[2] = 0.0;
-  if (n_q == 0) return LBM_OK;
-  HIPCHECK(c, hipStreamSynchronize(c->stream));
+}  // extern "C"
+
+namespace {
+
+// Doubles of wall-force workspace for n_q points: points, normals, weights,
+// tractions, partial sums, reduced sums.
+size_t force_ws_need(const lbm_ctx* c, int n_q) {
+  const size_t np = (size_t)(n_q + force_points_per_workgroup(c->Q) - 1) /
+                    (size_t)force_points_per_workgroup(c->Q);
+  return (size_t)n_q * (3 * c->D + 1) + np * 4 + 8;
+}
+
+// Wall force through the workspace ws (force_ws_need doubles): uploads the points,
+// runs the force kernel and the fixed-order reduction on the context stream,
+// copies the results out.  No allocation.
+lbm_status wall_force_run(lbm_ctx* c, int inst, const double* xq, const double* nq,
+                          const double* wq, int n_q, double* traction, double force[3],
+                          double* ws) {
   const int D = c->D;
-  const int np_max = (n_q + 255) / 256;
-  double* dm = nullptr;
-  const size_t nd = (size_t)n_q * D * 3 + n_q + (size_t)np_max * 4 + 8;
-  if ((st = dev_alloc(c, nd * sizeof(double), (void**)&dm))) return st;
-  double *dx = dm, *dn = dx + (size_t)n_q * D, *dw = dn + (size_t)n_q * D, *dt = dw + n_q;
-  double *dp = dt + (size_t)n_q * D, *dout = dp + (size_t)np_max * 4;
+  const size_t np_max = (size_t)(n_q + force_points_per_workgroup(c->Q) - 1) /
+                        (size_t)force_points_per_workgroup(c->Q);
+  double *dx = ws, *dn = dx + (size_t)n_q * D, *dw = dn + (size_t)n_q * D, *dt = dw + n_q;
+  double *dp = dt + (size_t)n_q * D, *dout = dp + np_max * 4;
   int np = 0;
   double sums[4] = {0, 0, 0, 0};
   hipError_t e = hipMemcpyAsync(dx, xq, (size_t)n_q * D * sizeof(double), hipMemcpyHostToDevice, c->stream);
@@ -988,11 +996,44 @@ lbm_status lbm_wall_force(lbm_ctx* c, int inst, const double* xq, const double* 
   if (e == hipSuccess && traction)
     e = hipMemcpyAsync(traction, dt, (size_t)n_q * D * sizeof(double), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  dev_free(c, dm);
   if (e != hipSuccess) return fail(c, LBM_ERR_DEVICE, "wall force: %s", hipGetErrorString(e));
   for (int a = 0; a < D; ++a) force[a] = sums[a];
-  if (sums[3] != 0.0) return fail(c, LBM_ERR_GEOMETRY, "%d quadrature points found no fluid node near a probe", (int)sums[3]);
+  if (sums[3] != 0.0)
+    return fail(c, LBM_ERR_GEOMETRY, "%d probes found no fluid node within two spacings", (int)sums[3]);
   return LBM_OK;
+}
+
+lbm_status wall_force_args(lbm_ctx* c, int inst, const double* xq, const double* nq,
+                           const double* wq, int n_q, double force[3]) {
+  lbm_status st = check_inst(c, inst);
+  if (st) return st;
+  if (!force || n_q < 0 || (n_q > 0 && (!xq || !nq || !wq)))
+    return fail(c, LBM_ERR_INVALID, "bad quadrature arguments");
+  if (!c->force_valid[inst])
+    return fail(c, LBM_ERR_INVALID, "wall force needs a step after the last geometry or state change");
+  force[0] = force[1] = force[2] = 0.0;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_wall_force(lbm_ctx* c, int inst, const double* xq, const double* nq,
+                          const double* wq, int n_q, double* traction, double force[3]) {
+  lbm_status st = wall_force_args(c, inst, xq, nq, wq, n_q, force);
+  if (st || n_q == 0) return st;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  // The workspace persists across calls and grows only for a larger n_q.
+  const size_t need = force_ws_need(c, n_q);
+  if (need > c->force_ws_doubles) {
+    dev_free(c, c->force_ws);
+    c->force_ws = nullptr;
+    c->force_ws_doubles = 0;
+    if ((st = dev_alloc(c, need * sizeof(double), (void**)&c->force_ws))) return st;
+    c->force_ws_doubles = need;
+  }
+  return wall_force_run(c, inst, xq, nq, wq, n_q, traction, force, c->force_ws);
 }
 
 lbm_status lbm_get_populations(lbm_ctx* c, int inst, double* f) {

@@ -1374,40 +1374,16 @@ __device__ void node_stress(const InstDev& I, const typename Store<ST>::T* sb, c
   if (dims<Q>() == 2) sig[2] = sig[4] = sig[5] = 0.0;
 }
 
-// Stress at an off-lattice point: (bi/tri)linear over the surrounding fluid
-// nodes with renormalised weights, else the nearest fluid node in the 5^D box
-// around floor(p) (first in z, y, x order on ties).
+// Probe stress when no stencil corner of the probe p is fluid: the nearest
+// fluid node in the 5^D box around floor(p) (Euclidean distance, first in z,
+// y, x order on ties).  Returns false if the box holds no fluid node.
 template <int Q, int ST>
-__device__ bool point_stress(const InstDev& I, const typename Store<ST>::T* sb, const uint8_t* fl,
-                             const double (&p)[3], double t, double (&sig)[6]) {
+__device__ bool nearest_fluid_stress(const InstDev& I, const typename Store<ST>::T* sb,
+                                     const uint8_t* fl, const double (&p)[3], double t,
+                                     double (&sig)[6]) {
   constexpr int D = dims<Q>();
   int base[3] = {0, 0, 0};
-  double fr[3] = {0.0, 0.0, 0.0};
-  for (int a = 0; a < D; ++a) {
-    base[a] = (int)floor(p[a]);
-    fr[a] = p[a] - base[a];
-  }
-  double acc[6] = {0, 0, 0, 0, 0, 0}, wsum = 0.0;
-  for (int k = 0; k < (1 << D); ++k) {
-    int off[3] = {0, 0, 0};
-    double w = 1.0;
-    for (int a = 0; a < D; ++a) {
-      off[a] = (k >> a) & 1;
-      w *= off[a] ? fr[a] : 1.0 - fr[a];
-    }
-    if (w <= 0.0) continue;
-    uint32_t m;
-    if (!resolve_nb(I, base[0], base[1], base[2], off[0], off[1], off[2], m)) continue;
-    if (fl && (fl[m] & FLAG_SOLID)) continue;
-    double s[6];
-    node_stress<Q, ST>(I, sb, fl, m, t, s);
-    for (int e = 0; e < 6; ++e) acc[e] += w * s[e];
-    wsum += w;
-  }
-  if (wsum > 0.0) {
-    for (int e = 0; e < 6; ++e) sig[e] = acc[e] / wsum;
-    return true;
-  }
+  for (int a = 0; a < D; ++a) base[a] = (int)floor(p[a]);
   double best = 1e300;
   int64_t bestm = -1;
   const int zr = D == 3 ? 2 : 0;
@@ -1433,42 +1409,93 @@ __device__ bool point_stress(const InstDev& I, const typename Store<ST>::T* sb, 
   return true;
 }
 
+// Wall force (Sec. II.C.2).  For quadrature point q the stress is sampled at
+// the probes p_k = x_q + k n_q (k = 1, 2): multilinear over the 2^D stencil
+// corners that are fluid, weights renormalised, else the nearest fluid node
+// (nearest_fluid_stress); sigma_q = 2 sigma(p_1) - sigma(p_2), t_q = sigma_q
+// n_q, and the workgroup's partial sum of w_q t_q.  One lane per (point,
+// probe, corner): each reconstructs one node's pre-collision stress, so the
+// 2 * 2^D reconstructions of a point run in parallel; lane 0 of the point
+// sums its corners in corner order and forms the traction.  64 / (2 * 2^D)
+// points per workgroup.  partials[4 * block] = (sum w t, count of probes
+// that found no fluid node).
 template <int Q, int ST>
-__global__ void __launch_bounds__(256) k_force(const InstDev* __restrict__ insts, int inst,
-                                               const void* prev, const uint8_t* flags,
-                                               const int64_t* clock, const double* xq,
-                                               const double* nq, const double* wq, int nqp,
-                                               double* traction, double* partials) {
+__global__ void __launch_bounds__(64) k_force(const InstDev* __restrict__ insts, int inst,
+                                              const void* prev, const uint8_t* flags,
+                                              const int64_t* clock, const double* xq,
+                                              const double* nq, const double* wq, int nqp,
+                                              double* traction, double* partials) {
   constexpr int D = dims<Q>();
+  constexpr int NC = 1 << D;    // stencil corners of a probe
+  constexpr int SL = 2 * NC;    // lanes per point
+  constexpr int PPW = 64 / SL;  // points per workgroup
+  __shared__ double s_sig[64][6];
+  __shared__ double s_w[64];
   const InstDev& I = insts[inst];
   const typename Store<ST>::T* sb = static_cast<const typename Store<ST>::T*>(prev) + I.pop_off;
   const uint8_t* fl = I.flag_off >= 0 ? flags + I.flag_off : nullptr;
   const double t = (double)(*clock);
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int lane = threadIdx.x, slot = lane % SL;
+  const int q = blockIdx.x * PPW + lane / SL;
+  const int k = slot / NC, corner = slot % NC;
+  double sig[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double w = 0.0;
+  double nv[3] = {0.0, 0.0, 0.0}, p[3] = {0.0, 0.0, 0.0};
   if (q < nqp) {
-    double nv[3] = {0, 0, 0}, p1[3] = {0, 0, 0}, p2[3] = {0, 0, 0};
     for (int a = 0; a < D; ++a) {
       nv[a] = nq[q * D + a];
-      p1[a] = xq[q * D + a] + nv[a];
-      p2[a] = xq[q * D + a] + 2.0 * nv[a];
+      p[a] = xq[q * D + a] + (k + 1) * nv[a];
     }
-    double s1[6], s2[6];
-    const bool ok1 = point_stress<Q, ST>(I, sb, fl, p1, t, s1);
-    const bool ok2 = point_stress<Q, ST>(I, sb, fl, p2, t, s2);
-    double S[3][3];
+    int base[3] = {0, 0, 0}, off[3] = {0, 0, 0};
+    w = 1.0;
+    for (int a = 0; a < D; ++a) {
+      base[a] = (int)floor(p[a]);
+      const double fr = p[a] - base[a];
+      off[a] = (corner >> a) & 1;
+      w *= off[a] ? fr : 1.0 - fr;
+    }
+    uint32_t m;
+    if (w > 0.0 && resolve_nb(I, base[0], base[1], base[2], off[0], off[1], off[2], m) &&
+        !(fl && (fl[m] & FLAG_SOLID))) {
+      node_stress<Q, ST>(I, sb, fl, m, t, sig);
+      for (int e = 0; e < 6; ++e) sig[e] *= w;
+    } else {
+      w = 0.0;
+    }
+  }
+  for (int e = 0; e < 6; ++e) s_sig[lane][e] = sig[e];
+  s_w[lane] = w;
+  __syncthreads();
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (slot == 0 && q < nqp) {
+    double S[2][6];
+    int missing = 0;
+    for (int kk = 0; kk < 2; ++kk) {
+      double a6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, wsum = 0.0;
+      for (int cc = 0; cc < NC; ++cc) {
+        const int l = lane + kk * NC + cc;
+        if (s_w[l] <= 0.0) continue;
+        for (int e = 0; e < 6; ++e) a6[e] += s_sig[l][e];
+        wsum += s_w[l];
+      }
+      if (wsum > 0.0) {
+        for (int e = 0; e < 6; ++e) S[kk][e] = a6[e] / wsum;
+      } else {
+        double pk[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < D; ++a) pk[a] = xq[q * D + a] + (kk + 1) * nv[a];
+        if (!nearest_fluid_stress<Q, ST>(I, sb, fl, pk, t, S[kk])) ++missing;
+      }
+    }
     const int ix[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
-    for (int a = 0; a < 3; ++a)
-      for (int c = 0; c < 3; ++c) S[a][c] = 2.0 * s1[ix[a][c]] - s2[ix[a][c]];
     for (int a = 0; a < D; ++a) {
       double ta = 0.0;
-      for (int c = 0; c < D; ++c) ta += S[a][c] * nv[c];
+      for (int c = 0; c < D; ++c) ta += (2.0 * S[0][ix[a][c]] - S[1][ix[a][c]]) * nv[c];
       if (traction) traction[q * D + a] = ta;
       acc[a] = wq[q] * ta;
     }
-    acc[3] = (ok1 && ok2) ? 0.0 : 1.0;
+    acc[3] = (double)missing;
   }
-  block_sum_doubles<256, 4>(acc, partials + 4 * blockIdx.x);
+  block_sum_doubles<64, 4>(acc, partials + 4 * blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1593,6 +1620,8 @@ static hipError_t launch_boundary(const StepBuffers& b, const Region* regions,
 
 int boundary_nodes_per_workgroup(int Q) { return Q == 27 ? 1 : 2; }
 
+int force_points_per_workgroup(int Q) { return Q == 27 ? 4 : 8; }
+
 template <int Q, int ST>
 static hipError_t launch_geometry(int stage, const InstDev* insts, const Region* regions,
                                   const BoxTile* gtiles, int ngt, void* src, uint8_t* flags,
@@ -1645,10 +1674,11 @@ static hipError_t launch_force(const InstDev* insts, int inst, const void* prev,
                                const uint8_t* flags, const int64_t* clock, const double* xq,
                                const double* nq, const double* wq, int nqp, double* traction,
                                double* partials, int* nparts, hipStream_t s) {
-  const unsigned g = grid_for(nqp, 256);
+  const unsigned g = (unsigned)((nqp + force_points_per_workgroup(Q) - 1) /
+                                force_points_per_workgroup(Q));
   *nparts = (int)g;
   if (g == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_force<Q, ST>), dim3(g), dim3(256), 0, s, insts, inst, prev, flags, clock,
+  hipLaunchKernelGGL((k_force<Q, ST>), dim3(g), dim3(64), 0, s, insts, inst, prev, flags, clock,
                      xq, nq, wq, nqp, traction, partials);
   return hipGetLastError();
 }

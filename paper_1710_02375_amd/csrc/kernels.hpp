@@ -79,7 +79,8 @@ struct Ops {
   // stats[stat0 + workgroup].  It also ends the step: clears neq_next and
   // advances clock_tick.
   hipError_t (*fixup)(const StepBuffers& b, int nblocks, int stat0, hipStream_t s);
-  // Wall force (per point traction, per-workgroup partial force sums).
+  // Wall force (per point traction, per-workgroup partial force sums: four
+  // doubles per workgroup, force_points_per_workgroup(Q) points each).
   hipError_t (*force)(const InstDev* insts, int inst, const void* prev, const uint8_t* flags,
                       const int64_t* clock, const double* xq, const double* nq,
                       const double* wq, int nqp, double* traction, double* partials,
@@ -90,6 +91,10 @@ const Ops* get_ops(int Q, int storage);
 
 // Boundary nodes handled by one workgroup (wavefront) at a time.
 int boundary_nodes_per_workgroup(int Q);
+
+// Quadrature points per workgroup of the wall-force kernel (its partial-sum
+// count is ceil(n_q / this)).
+int force_points_per_workgroup(int Q);
 
 // Bulk-kernel variants (workgroup size, nodes per tile, waves per SIMD hint).
 int bulk_variant_count();

@@ -169,11 +169,13 @@ class TorchAllocator:
         self.device = device
         self.stream = stream
         self._live = {}
+        self.n_alloc = 0   # allocation callbacks served
         self.alloc_fn = ALLOC_FN(self._alloc)
         self.free_fn = FREE_FN(self._free)
 
     def _alloc(self, nbytes, _ctx):
         torch = self._torch
+        self.n_alloc += 1
         dev = "cuda:%d" % self.device
         if self.stream is not None:
             with torch.cuda.stream(self.stream):
