@@ -232,7 +232,7 @@ def sphere_form(lbm, torch, storage, steps, sample_every, variant=None, dims=(51
     U, R = cfg["U"], cfg["radius"]
     norm = 0.5 * U * U * math.pi * R * R
     series = []
-    t_force = []
+    t_force, t_force_na = [], []
     t_step = 0.0
     done = 0
     while done < steps:
@@ -248,13 +248,17 @@ def sphere_form(lbm, torch, storage, steps, sample_every, variant=None, dims=(51
         t0 = time.perf_counter()
         F, _ = s.wall_force(xq, nq, wq)
         t_force.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        lbm.lbm_wall_force_noalloc(s.ctx, 0, xq, nq, wq, 3)
+        t_force_na.append(time.perf_counter() - t0)
         series.append((done, F[0] / norm, F[1] / norm, F[2] / norm))
     _, uu, tot = s.moments()
     s.close()
     # The first call allocates the persistent workspace; report the median.
     return {"MLUPS": round(N * steps / t_step / 1e6, 1), "ms_per_step": round(t_step * 1e3 / steps, 5),
             "series": series, "u": uu, "mass": tot["mass"],
-            "wall_force_ms_5120_points": round(1e3 * float(np.median(t_force)), 4)}
+            "wall_force_ms_5120_points": round(1e3 * float(np.median(t_force)), 4),
+            "wall_force_noalloc_ms_5120_points": round(1e3 * float(np.median(t_force_na)), 4)}
 
 
 def sphere_workload(lbm, torch, args):
@@ -269,6 +273,7 @@ def sphere_workload(lbm, torch, args):
             ref = r
         entry = {"MLUPS": r["MLUPS"], "ms_per_step": r["ms_per_step"],
                  "wall_force_ms_5120_points": r["wall_force_ms_5120_points"],
+                 "wall_force_noalloc_ms_5120_points": r["wall_force_noalloc_ms_5120_points"],
                  "Cd_Cl_last": [round(v, 6) for v in r["series"][-1][1:3]]}
         if storage != "f64":
             a, b = np.array(r["series"])[:, 1:3], np.array(ref["series"])[:, 1:3]

@@ -207,6 +207,19 @@ lbm_status lbm_moments(lbm_ctx* ctx, int inst, double* rho, double* u, lbm_total
 lbm_status lbm_wall_force(lbm_ctx* ctx, int inst, const double* xq, const double* nq,
                           const double* wq, int n_q, double* traction, double force[3]);
 
+/* lbm_wall_force for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving or coupling loops, harnesses that forbid
+ * allocation): same arguments, kernels and results, but its workspace is a
+ * static device array of the library (5.8 MB per GPU, kept until the process
+ * ends) instead of memory the context allocates, and the call makes no
+ * device allocation or release.  n_q is limited to 65536 points (larger
+ * requests return LBM_ERR_INVALID).  Every call on one GPU shares that
+ * workspace: calls that overlap on one GPU (several contexts on different
+ * streams or threads) race and must be serialised by the caller.
+ * Synchronous. */
+lbm_status lbm_wall_force_noalloc(lbm_ctx* ctx, int inst, const double* xq, const double* nq,
+                                  const double* wq, int n_q, double* traction, double force[3]);
+
 /* Checkpoint: copies the populations of instance inst to / from the host
  * (Q*N doubles, population-major, full f_i).  A set is rounded to the
  * storage format.  Resuming from get -> set is bitwise exact. */

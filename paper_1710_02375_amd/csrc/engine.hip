@@ -11,6 +11,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -24,6 +25,16 @@ using namespace kbc;
 static constexpr int kFixupBlocks = 512;
 // Upper bound on the one-wavefront workgroups of a boundary launch.
 static constexpr int kBoundaryWorkgroups = 4096;
+
+// Static workspace of lbm_wall_force_noalloc: quadrature points, normals,
+// weights and tractions (3 D + 1 doubles per point, D <= 3), the force
+// kernel's partial sums (four doubles per workgroup of at least four points)
+// and the reduced sums, for up to kNoAllocMaxPoints points.  5.8 MB, held by
+// every GPU the library runs on until the process ends.
+static constexpr int kNoAllocMaxPoints = 65536;
+static constexpr size_t kForceScratchDoubles =
+    (size_t)kNoAllocMaxPoints * 10 + ((size_t)kNoAllocMaxPoints / 4 + 1) * 4 + 8;
+static __device__ __align__(256) double scratch[kForceScratchDoubles];
 
 struct lbm_ctx {
   int device = 0;
@@ -44,6 +55,7 @@ struct lbm_ctx {
   std::vector<char> force_valid;
   double* force_ws = nullptr;     // wall-force workspace, grown on demand
   size_t force_ws_doubles = 0;
+  double* scratch = nullptr;      // device address of `scratch` on this device
   int64_t total_nodes = 0;
   size_t pop_elems = 0;           // elements per population buffer
 
@@ -118,6 +130,30 @@ lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
     if (e_ != hipSuccess)                                                                      \
       return fail((ctx), LBM_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
   } while (0)
+
+// Device address of the static wall-force workspace on the context's device,
+// resolved once per device (with that device current) and kept.  In host
+// code `scratch` names a host-side stand-in, never the device memory.
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;
+
+lbm_status resolve_scratch(lbm_ctx* c) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(c->device);
+  if (it != g_scratch_ptr.end()) {
+    c->scratch = it->second;
+    return LBM_OK;
+  }
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr) {
+    (void)hipGetLastError();
+    return fail(c, LBM_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+  }
+  g_scratch_ptr[c->device] = static_cast<double*>(ptr);
+  c->scratch = static_cast<double*>(ptr);
+  return LBM_OK;
+}
 
 lbm_status dev_alloc(lbm_ctx* c, size_t bytes, void** p) {
   *p = nullptr;
@@ -660,6 +696,7 @@ lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_
     }
     c->own_stream = true;
   }
+  if ((st = resolve_scratch(c))) return bail(st);
   // Layout: per instance Q population arrays of stride round_up(N, 64).
   c->hinst.resize(n_instances);
   c->moving.assign(n_instances, 0);
@@ -1034,6 +1071,19 @@ lbm_status lbm_wall_force(lbm_ctx* c, int inst, const double* xq, const double* 
     c->force_ws_doubles = need;
   }
   return wall_force_run(c, inst, xq, nq, wq, n_q, traction, force, c->force_ws);
+}
+
+lbm_status lbm_wall_force_noalloc(lbm_ctx* c, int inst, const double* xq, const double* nq,
+                                  const double* wq, int n_q, double* traction, double force[3]) {
+  lbm_status st = wall_force_args(c, inst, xq, nq, wq, n_q, force);
+  if (st || n_q == 0) return st;
+  if (n_q > kNoAllocMaxPoints)
+    return fail(c, LBM_ERR_INVALID, "n_q = %d exceeds the %d points of the static workspace", n_q,
+                kNoAllocMaxPoints);
+  if (force_ws_need(c, n_q) > kForceScratchDoubles)
+    return fail(c, LBM_ERR_INVALID, "static workspace too small for n_q = %d", n_q);
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  return wall_force_run(c, inst, xq, nq, wq, n_q, traction, force, c->scratch);
 }
 
 lbm_status lbm_get_populations(lbm_ctx* c, int inst, double* f) {

@@ -94,6 +94,8 @@ def lib():
         L.lbm_moments.argtypes = [vp, C.c_int, vp, vp, C.POINTER(lbm_totals)]
         L.lbm_wall_force.argtypes = [vp, C.c_int, _dp, _dp, _dp, C.c_int, vp,
                                      C.POINTER(C.c_double)]
+        L.lbm_wall_force_noalloc.argtypes = [vp, C.c_int, _dp, _dp, _dp, C.c_int, vp,
+                                             C.POINTER(C.c_double)]
         L.lbm_get_populations.argtypes = [vp, C.c_int, _dp]
         L.lbm_set_populations.argtypes = [vp, C.c_int, _dp]
         L.lbm_set_stats.argtypes = [vp, C.c_int]
@@ -115,7 +117,7 @@ def lib():
 
 
 EXPORTED = ["lbm_create", "lbm_destroy", "lbm_init_fields", "lbm_set_geometry", "lbm_step",
-            "lbm_moments", "lbm_wall_force", "lbm_get_populations", "lbm_set_populations",
+            "lbm_moments", "lbm_wall_force", "lbm_wall_force_noalloc", "lbm_get_populations", "lbm_set_populations",
             "lbm_set_stats", "lbm_set_launch_mode", "lbm_autotune", "lbm_set_variant",
             "lbm_variant_count", "lbm_variant_name", "lbm_info", "lbm_synchronize",
             "lbm_status_string", "lbm_last_error"]
@@ -273,6 +275,19 @@ def lbm_wall_force(ctx, inst, xq, nq, wq, D, want_traction=True):
     F = (C.c_double * 3)()
     st = lib().lbm_wall_force(ctx, int(inst), xq, nq, wq, n,
                               tr.ctypes.data if want_traction else None, F)
+    _check(ctx, st)
+    return np.array(F[:D]), (tr.reshape(n, D) if want_traction else None)
+
+
+def lbm_wall_force_noalloc(ctx, inst, xq, nq, wq, D, want_traction=True):
+    """lbm_wall_force through the library's static workspace (no device
+    allocation; at most 65536 points)."""
+    xq, nq, wq = _f64(xq), _f64(nq), _f64(wq)
+    n = wq.size
+    tr = np.zeros(n * D) if want_traction else None
+    F = (C.c_double * 3)()
+    st = lib().lbm_wall_force_noalloc(ctx, int(inst), xq, nq, wq, n,
+                                      tr.ctypes.data if want_traction else None, F)
     _check(ctx, st)
     return np.array(F[:D]), (tr.reshape(n, D) if want_traction else None)
 
