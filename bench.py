@@ -185,6 +185,11 @@ def batched_form(lbm, torch, steps, warmup, count=64):
             s.init_fields(np.ones(N), np.zeros((2, N)), inst=k)
             s.set_body(*c["body"], inst=k)
         s.set_launch_mode(mode)
+        if mode == 0:
+            v = lbm.lbm_autotune(s.ctx, os.environ.get("KBC_AUTOTUNE_CACHE"))
+            out["variant"] = lbm.lbm_variant_name(v)
+        else:
+            lbm.lbm_set_variant(s.ctx, v)
         s.step(warmup)
         stream.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -261,13 +266,13 @@ def sphere_form(lbm, torch, storage, steps, sample_every, variant=None, dims=(51
             "wall_force_noalloc_ms_5120_points": round(1e3 * float(np.median(t_force_na)), 4)}
 
 
-def sphere_workload(lbm, torch, args):
+def sphere_workload(lbm, torch, args, forms=("f64", "f32", "f16")):
     """Config: D3Q27 channel 512x128x128, oscillating sphere R=16, Re=300;
     FP32 and FP16-shifted against the FP64 form of the same kernel (itself
     checked against the CPU oracle on a scaled copy in the test suite)."""
     out = {}
     ref = None
-    for storage in ("f64", "f32", "f16"):
+    for storage in forms:
         r = sphere_form(lbm, torch, storage, args.sphere_steps, args.sphere_sample)
         if ref is None:
             ref = r
@@ -334,9 +339,14 @@ def _cpu_model():
     return None
 
 
-def cpu_baseline(seconds=12.0, one_thread_seconds=6.0):
-    """The oracle as it stands, on a bounded sample of the workload: all host
-    threads (the reported value), then one thread for reference."""
+def cpu_baseline(seconds=12.0, one_thread_seconds=6.0, sphere_seconds=20.0, sphere_steps=None):
+    """The oracle as it stands, on bounded samples of the workloads: the
+    headline Taylor-Green case on 64^3 with all host threads (the reported
+    value) and with one thread; the D2Q9 Taylor-Green 64^2 run of 500 steps in
+    full; the sphere channel 512x128x128 for as many steps as fit in
+    sphere_seconds (or exactly sphere_steps steps)."""
+    import math
+
     import oracle
     import workloads as W
 
@@ -359,10 +369,39 @@ def cpu_baseline(seconds=12.0, one_thread_seconds=6.0):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     v, steps, el = run(threads, seconds)
     v1, steps1, el1 = run(1, one_thread_seconds)
+    samples = {}
+    # D2Q9 Taylor-Green 64^2, FP64, 500 steps, in full.
+    r2, u2 = W.taylor_green_2d(64, 0.02)
+    d = oracle.Domain(9, 64, 64, 1, 0.01)
+    d.init_fields(r2, u2)
+    t0 = time.perf_counter()
+    d.step(500)
+    el2 = time.perf_counter() - t0
+    samples["d2q9_tg_64x64_500_steps"] = {"MLUPS": 64 * 64 * 500 / el2 / 1e6, "seconds": el2}
+    # Sphere channel, bounded.
+    cfg = W.sphere_channel()
+    nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
+    N = nx * ny * nz
+    d = oracle.Domain(27, nx, ny, nz, cfg["nu"], faces=cfg["faces"], u_in=cfg["u_in"],
+                      ramp_steps=cfg["ramp_steps"])
+    d.init_fields(np.ones(N), np.zeros((3, N)))
+    d.set_body(*cfg["body"])
+    d.step(1)
+    k = 0
+    t0 = time.perf_counter()
+    while (sphere_steps is not None and k < sphere_steps) or \
+            (sphere_steps is None and time.perf_counter() - t0 < sphere_seconds):
+        d.step(1)
+        k += 1
+    el3 = time.perf_counter() - t0
+    del d
+    samples["sphere_channel_512x128x128"] = {"MLUPS": N * k / el3 / 1e6, "steps": k,
+                                             "seconds": el3}
     return {"value": v, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": "D3Q27 KBC Taylor-Green 64^3 periodic (same Re, Ma, perturbation), "
                       "FP64, %d steps in %.1f s" % (steps, el),
             "one_thread": {"value": v1, "sample": "%d steps in %.1f s" % (steps1, el1)},
+            "other_samples_all_threads": samples,
             "cpu_model": _cpu_model()}
 
 
@@ -382,8 +421,11 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64"])
     ap.add_argument("--workload", default="tg256", choices=["tg256", "tg512", "sphere", "batched"],
                     help="tg256 is the headline line; the others print their own line")
-    ap.add_argument("--sphere-steps", type=int, default=2000)
-    ap.add_argument("--sphere-sample", type=int, default=100)
+    ap.add_argument("--sphere-steps", type=int, default=1200)
+    ap.add_argument("--sphere-sample", type=int, default=200)
+    ap.add_argument("--cpu-sphere-steps", type=int, default=None,
+                    help="oracle steps of the sphere channel in the CPU baseline "
+                         "(default: as many as fit in 20 s)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus %d requested); the "
@@ -450,6 +492,8 @@ def main():
                                          "variant": i2["variant"]}
         var["batched_d2q9_flap_channels_f32"] = batched_form(lbm, torch, args.batched_steps,
                                                              args.batched_warmup)
+        sph = sphere_workload(lbm, torch, args)
+        var["sphere_channel"] = {"config": sph["config"], "forms": sph["forms"]}
         timed = {args.storage: info["variant"], "f16": var["f16_shifted"]["variant"],
                  "bf16": var["bf16_shifted"]["variant"]}
         err = error_vs_f64(lbm, n, rho, u, nu, args.error_steps, timed)
@@ -457,7 +501,7 @@ def main():
         var["velocity_rel_l2_variants"] = timed
         result["variants"] = var
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline()
+        result["cpu_baseline"] = cpu_baseline(sphere_steps=args.cpu_sphere_steps)
     print(json.dumps(result), flush=True)
 
 

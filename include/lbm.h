@@ -62,7 +62,8 @@ typedef int lbm_status;
 #define LBM_LBGK 1
 
 /* Face conditions, faces ordered -x, +x, -y, +y, -z, +z.  PERIODIC must be
- * paired; INLET is allowed on -x only, OUTLET on +x only.
+ * paired; INLET is allowed on -x only, OUTLET on +x only, and either needs
+ * nx >= 2.
  *   INLET : equilibrium at the inflow velocity and the lagged density of the
  *           interior neighbour (parabolic profile option, smooth ramp).
  *   OUTLET: equilibrium at density 1 and the lagged velocity of the upstream
@@ -225,6 +226,14 @@ lbm_status lbm_wall_force_noalloc(lbm_ctx* ctx, int inst, const double* xq, cons
  * storage format.  Resuming from get -> set is bitwise exact. */
 lbm_status lbm_get_populations(lbm_ctx* ctx, int inst, double* f);
 lbm_status lbm_set_populations(lbm_ctx* ctx, int inst, const double* f);
+/* Copies the populations of the box [lo, hi) of instance inst to the host
+ * ((hi-lo) product * Q doubles, population-major over the box's own
+ * x-fastest node order, full f_i), e.g. a crop with its halo for checking one
+ * step elsewhere.  Along a periodic axis the box may wrap once (lo >= -n,
+ * hi <= 2n, at most n wide); along other axes 0 <= lo < hi <= n, else
+ * LBM_ERR_INVALID.  Synchronous. */
+lbm_status lbm_get_populations_box(lbm_ctx* ctx, int inst, const int lo[3], const int hi[3],
+                                   double* f);
 
 /* Switches per-step statistics (gamma min/mean/max, FP64-path share) on or
  * off; off by default because it adds a reduction to every step.  Nodes with

@@ -52,6 +52,8 @@ struct lbm_ctx {
   std::vector<InstDev> hinst;
   std::vector<int> moving;        // body moves (geometry changes every step)
   std::vector<char> has_body;
+  std::vector<char> has_faces;    // an inflow or outflow face
+  bool any_faces = false;
   std::vector<char> force_valid;
   double* force_ws = nullptr;     // wall-force workspace, grown on demand
   size_t force_ws_doubles = 0;
@@ -71,8 +73,10 @@ struct lbm_ctx {
                                   // a step with source buffer k appends to [k]
   int last_src = -1;              // source buffer of the last step enqueued
   uint2* dneq_list = nullptr;
-  // Boundary node lists (two per launch: nodes with missing populations,
-  // then inflow / outflow plane nodes): instance k's pair starts at
+  // Boundary node lists (two per launch: nodes with a cut link to a body,
+  // then nodes whose missing populations all come from wall faces; inflow
+  // and outflow plane nodes are formed by the bulk kernel): instance k's
+  // pair starts at
   // 2 bl_off[k] (capacity bl_cap[k] each, its box-tile volume); the batched
   // launch uses the whole allocation with capacity bl_total.  Counter pairs:
   // [2k, 2k+1] per instance, [2 n_inst, 2 n_inst + 1] batched.
@@ -81,8 +85,10 @@ struct lbm_ctx {
   uint32_t* dbcount = nullptr;
   std::vector<uint32_t> bl_off, bl_cap;
   uint32_t bl_total = 0;
-  int bl_nwg_all = 0, bl_nfb_all = 0; // workgroups of the batched boundary launch
-  std::vector<int> bl_nwg, bl_nfb, bl_stat;   // per instance, and stats offsets
+  // Workgroups of the batched boundary launch: Grad wavefronts, wall-node
+  // threads (64 per workgroup).
+  int bl_nwg_all = 0, bl_nwall_all = 0;
+  std::vector<int> bl_nwg, bl_nwall, bl_stat;   // per instance, and stats offsets
   int bstat_slots = 0;                // stats slots reserved for boundary launches
   hipEvent_t err_event = nullptr;
   bool err_pending = false;
@@ -354,31 +360,41 @@ lbm_status rebuild_work(lbm_ctx* c) {
     auto nwg_for = [&](uint32_t cap) {
       return (int)std::min<uint64_t>(kBoundaryWorkgroups, (cap + ng - 1) / ng);
     };
-    auto nfb_for = [&](uint32_t cap) {
+    auto nwall_for = [&](uint32_t cap) {
       return (int)std::min<uint64_t>(kBoundaryWorkgroups, (cap + 63) / 64);
     };
     c->bl_off.assign(c->n_inst, 0);
     c->bl_cap.assign(c->n_inst, 0);
     c->bl_nwg.assign(c->n_inst, 0);
-    c->bl_nfb.assign(c->n_inst, 0);
+    c->bl_nwall.assign(c->n_inst, 0);
     c->bl_stat.assign(c->n_inst, 0);
     uint32_t off = 0;
     int sum_nwg = 0;
+    // The Grad wavefront kernel serves nodes with a cut link to a body, the
+    // wall kernel nodes with wall faces only: neither runs without them.
+    bool any_body = false, any_wall = false;
+    std::vector<char> has_wall(c->n_inst, 0);
+    for (int k = 0; k < c->n_inst; ++k) {
+      for (int f = 0; f < 6; ++f)
+        if (c->desc[k].face[f] == LBM_FACE_WALL) has_wall[k] = 1;
+      any_wall = any_wall || has_wall[k];
+      any_body = any_body || c->has_body[k];
+    }
     for (int k = 0; k < c->n_inst; ++k) {
       uint32_t cap = 0;
       for (int t = c->bt_first[k]; t < c->bt_first[k] + c->bt_count[k]; ++t) cap += c->btiles[t].count;
       c->bl_off[k] = off;
       c->bl_cap[k] = cap;
-      c->bl_nwg[k] = nwg_for(cap);
-      c->bl_nfb[k] = nfb_for(cap);
+      c->bl_nwg[k] = c->has_body[k] ? nwg_for(cap) : 0;
+      c->bl_nwall[k] = has_wall[k] ? nwall_for(cap) : 0;
       c->bl_stat[k] = sum_nwg;
-      sum_nwg += c->bl_nwg[k] + c->bl_nfb[k];
+      sum_nwg += c->bl_nwg[k] + c->bl_nwall[k];
       off += cap;
     }
     c->bl_total = off;
-    c->bl_nwg_all = nwg_for(off);
-    c->bl_nfb_all = nfb_for(off);
-    c->bstat_slots = std::max(c->bl_nwg_all + c->bl_nfb_all, sum_nwg);
+    c->bl_nwg_all = any_body ? nwg_for(off) : 0;
+    c->bl_nwall_all = any_wall ? nwall_for(off) : 0;
+    c->bstat_slots = std::max(c->bl_nwg_all + c->bl_nwall_all, sum_nwg);
     if ((size_t)off > c->dblist_cap) {
       dev_free(c, c->dblist);
       c->dblist = nullptr;
@@ -447,17 +463,17 @@ lbm_status enqueue_step(lbm_ctx* c, int src) {
   const int nbt = (int)c->btiles.size();
   if (c->launch_mode == 0) {
     HIPCHECK(c, c->ops->boundary(b, c->dregions, c->dbtiles, 0, nbt, c->dblist, c->bl_total,
-                                 c->dbcount + 2 * c->n_inst, c->bl_nwg_all, c->bl_nfb_all, ntiles,
+                                 c->dbcount + 2 * c->n_inst, c->bl_nwg_all, c->bl_nwall_all, ntiles,
                                  c->stream));
-    HIPCHECK(c, c->ops->bulk(c->variant, b, c->dtiles, 0, ntiles, c->stream));
+    HIPCHECK(c, c->ops->bulk(c->variant, b, c->dtiles, 0, ntiles, c->any_faces, c->stream));
   } else {
     for (int k = 0; k < c->n_inst; ++k) {
       HIPCHECK(c, c->ops->boundary(b, c->dregions, c->dbtiles, c->bt_first[k], c->bt_count[k],
                                    c->dblist + 2 * (size_t)c->bl_off[k], c->bl_cap[k],
-                                   c->dbcount + 2 * k, c->bl_nwg[k], c->bl_nfb[k],
+                                   c->dbcount + 2 * k, c->bl_nwg[k], c->bl_nwall[k],
                                    ntiles + c->bl_stat[k], c->stream));
       HIPCHECK(c, c->ops->bulk(c->variant, b, c->dtiles, c->tile_first[k], c->tile_count[k],
-                               c->stream));
+                               c->has_faces[k] != 0, c->stream));
     }
   }
   HIPCHECK(c, c->ops->fixup(b, kFixupBlocks, ntiles + c->bstat_slots, c->stream));
@@ -651,6 +667,8 @@ lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_
     if (d.collision != LBM_KBC && d.collision != LBM_LBGK)
       return fail(nullptr, LBM_ERR_INVALID, "instance %d: unknown collision", k);
     if (!valid_faces(d)) return fail(nullptr, LBM_ERR_INVALID, "instance %d: invalid faces", k);
+    if ((d.face[0] == LBM_FACE_INLET || d.face[1] == LBM_FACE_OUTLET) && d.nx < 2)
+      return fail(nullptr, LBM_ERR_INVALID, "instance %d: inflow / outflow faces need nx >= 2", k);
     if (d.inlet_profile != 0 && d.inlet_profile != 1)
       return fail(nullptr, LBM_ERR_INVALID, "instance %d: unknown inlet profile", k);
     if (d.ramp_steps < 0) return fail(nullptr, LBM_ERR_INVALID, "instance %d: ramp < 0", k);
@@ -701,6 +719,11 @@ lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_
   c->hinst.resize(n_instances);
   c->moving.assign(n_instances, 0);
   c->has_body.assign(n_instances, 0);
+  c->has_faces.assign(n_instances, 0);
+  for (int k = 0; k < n_instances; ++k) {
+    c->has_faces[k] = desc[k].face[0] == LBM_FACE_INLET || desc[k].face[1] == LBM_FACE_OUTLET;
+    if (c->has_faces[k]) c->any_faces = true;
+  }
   c->force_valid.assign(n_instances, 0);
   // Population arrays are padded so that consecutive arrays do not start a
   // power of two apart (which maps the Q loads of a wave onto the same HBM
@@ -1099,6 +1122,33 @@ lbm_status lbm_get_populations(lbm_ctx* c, int inst, double* f) {
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   dev_free(c, df);
   if (e != hipSuccess) return fail(c, LBM_ERR_DEVICE, "get_populations: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
+lbm_status lbm_get_populations_box(lbm_ctx* c, int inst, const int lo[3], const int hi[3],
+                                   double* f) {
+  lbm_status st = check_inst(c, inst);
+  if (st) return st;
+  if (!f || !lo || !hi) return fail(c, LBM_ERR_INVALID, "f, lo and hi are required");
+  const lbm_instance_desc& d = c->desc[inst];
+  const int n[3] = {d.nx, d.ny, d.nz};
+  int ext[3];
+  for (int a = 0; a < 3; ++a) {
+    ext[a] = hi[a] - lo[a];
+    const bool periodic = d.face[2 * a] == LBM_FACE_PERIODIC;
+    const bool ok = ext[a] >= 1 && (periodic ? (lo[a] >= -n[a] && hi[a] <= 2 * n[a] && ext[a] <= n[a])
+                                             : (lo[a] >= 0 && hi[a] <= n[a]));
+    if (!ok) return fail(c, LBM_ERR_INVALID, "box [%d, %d) invalid along axis %d", lo[a], hi[a], a);
+  }
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  const int64_t Nb = (int64_t)ext[0] * ext[1] * ext[2];
+  double* df = nullptr;
+  if ((st = dev_alloc(c, (size_t)c->Q * Nb * sizeof(double), (void**)&df))) return st;
+  hipError_t e = c->ops->decode_box(c->dinst, inst, lo, ext, c->buf[c->cur], df, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(f, df, (size_t)c->Q * Nb * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_free(c, df);
+  if (e != hipSuccess) return fail(c, LBM_ERR_DEVICE, "get_populations_box: %s", hipGetErrorString(e));
   return LBM_OK;
 }
 

@@ -188,12 +188,13 @@ __device__ __forceinline__ void project_conserved(R (&dh)[Q]) {
 }
 
 // ---------------------------------------------------------------------------
-// gamma in FP64 for near-equilibrium nodes of the FP32 paths.  Streams over
-// the populations several times instead of holding FP64 arrays, so that the
-// rarely taken branch does not raise the register budget of the kernel.
+// gamma in FP64 for near-equilibrium nodes of the FP32 paths (only the
+// deferred FP64 pass calls it, so it holds Delta in registers): Delta in
+// FP64 from the stored values, its shear part, the conservation projection
+// of Delta h, and the two scalar products with weight 1/f^eq.
 // ---------------------------------------------------------------------------
 template <int Q>
-__device__ __noinline__ double gamma_fp64(const float (&d)[Q], double beta, int trace_in_s) {
+__device__ __forceinline__ double gamma_fp64(const float (&d)[Q], double beta, int trace_in_s) {
   double rt = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -208,17 +209,18 @@ __device__ __noinline__ double gamma_fp64(const float (&d)[Q], double beta, int 
 #pragma unroll
   for (int a = 0; a < dims<Q>(); ++a) A[a] = axis_eq(j[a] * ir);
   if (dims<Q>() == 2) A[2] = A[1];   // unused in 2D
-  // Pass 1: second moments of Delta.
+  // Delta and its second moments.
+  double dl[Q];
   double P[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double dl = (double)d[i] - weight<Q>(i) * (rt + rho * eq_E<Q>(A, i));
-    P[0] += cx(i) * cx(i) * dl;
-    P[1] += cy(i) * cy(i) * dl;
-    P[2] += cz<Q>(i) * cz<Q>(i) * dl;
-    P[3] += cx(i) * cy(i) * dl;
-    P[4] += cx(i) * cz<Q>(i) * dl;
-    P[5] += cy(i) * cz<Q>(i) * dl;
+    dl[i] = (double)d[i] - weight<Q>(i) * (rt + rho * eq_E<Q>(A, i));
+    P[0] += cx(i) * cx(i) * dl[i];
+    P[1] += cy(i) * cy(i) * dl[i];
+    P[2] += cz<Q>(i) * cz<Q>(i) * dl[i];
+    P[3] += cx(i) * cy(i) * dl[i];
+    P[4] += cx(i) * cz<Q>(i) * dl[i];
+    P[5] += cy(i) * cz<Q>(i) * dl[i];
   }
   Shear<Q, double> S;
   S.Pxy = P[3];
@@ -236,24 +238,22 @@ __device__ __noinline__ double gamma_fp64(const float (&d)[Q], double beta, int 
     S.Dzz = 0.0;
   }
   const double ts = trace_in_s ? S.T : 0.0;
-  // Pass 2: mass and momentum left in Delta h by rounding.
+  // Mass and momentum left in Delta h by rounding.
   double m = 0.0, J[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double dl = (double)d[i] - weight<Q>(i) * (rt + rho * eq_E<Q>(A, i));
-    const double h = dl - shear_pop<Q>(S, i, ts);
+    const double h = dl[i] - shear_pop<Q>(S, i, ts);
     m += h;
     J[0] += cx(i) * h;
     J[1] += cy(i) * h;
     J[2] += cz<Q>(i) * h;
   }
-  // Pass 3: the two scalar products with weight 1/f^eq.
+  // The two scalar products with weight 1/f^eq.
   double a = 0.0, b = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double dl = (double)d[i] - weight<Q>(i) * (rt + rho * eq_E<Q>(A, i));
     const double s = shear_pop<Q>(S, i, ts);
-    double h = dl - s;
+    double h = dl[i] - s;
     if (i == rest<Q>()) h -= m;
 #pragma unroll
     for (int ax = 0; ax < dims<Q>(); ++ax) {

@@ -155,16 +155,15 @@ __device__ void inflow_velocity(const InstDev& I, int y, int z, double t, double
 }
 
 // ---------------------------------------------------------------------------
-// Lagged moments (post-collision state stored at the node itself).
+// Lagged moments (post-collision state stored at the node itself), in the
+// arithmetic type R.
 // ---------------------------------------------------------------------------
-template <int Q, int ST>
+template <int Q, int ST, typename R>
 __device__ __forceinline__ void lagged(const typename Store<ST>::T* sb, int64_t stride, uint32_t m,
-                                       typename Store<ST>::R& rt,
-                                       typename Store<ST>::R (&u)[3]) {
-  using R = typename Store<ST>::R;
+                                       R& rt, R (&u)[3]) {
   R d[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) d[i] = Store<ST>::dec(sb[i * stride + m]);
+  for (int i = 0; i < Q; ++i) d[i] = (R)Store<ST>::dec(sb[i * stride + m]);
   R j[3];
   moments_dev<Q>(d, rt, j);
   const R ir = R(1) / (R(1) + rt);
@@ -172,18 +171,19 @@ __device__ __forceinline__ void lagged(const typename Store<ST>::T* sb, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// Pre-collision state of one node (any node: bulk, face or cut links):
-// pull streaming f_i(x) = A_i(x - c_i) (Eq. 1), missing populations from
-// Grad's approximation (Sec. II.C.1), inflow / outflow equilibria.
+// Pre-collision state of one node (any node: bulk, face or cut links) in
+// the arithmetic type R: pull streaming f_i(x) = A_i(x - c_i) (Eq. 1),
+// missing populations from Grad's approximation (Sec. II.C.1), inflow /
+// outflow equilibria.
 //   sb   : instance base of the state being streamed (post-collision at t-1)
 //   t1   : time of the new state (geometry and inflow ramp)
-// Returns the deviations f_i - W_i.
+// Returns the deviations f_i - W_i.  Each neighbour's lagged moments are
+// read only where the chosen interpolation or difference uses them.
 // ---------------------------------------------------------------------------
-template <int Q, int ST>
+template <int Q, int ST, typename R>
 __device__ void gather_pre(const InstDev& I, const typename Store<ST>::T* sb, const uint8_t* fl,
-                           int x, int y, int z, double t1, typename Store<ST>::R (&f)[Q]) {
+                           int x, int y, int z, double t1, R (&f)[Q]) {
   using S = Store<ST>;
-  using R = typename S::R;
   constexpr int D = dims<Q>();
   const int64_t stride = I.stride;
   const int n[3] = {I.nx, I.ny, I.nz};
@@ -213,7 +213,7 @@ __device__ void gather_pre(const InstDev& I, const typename Store<ST>::T* sb, co
     } else {
       const uint32_t m = node_index(I, s[0], s[1], s[2]);
       if (fl && (fl[m] & FLAG_SOLID)) miss |= 1u << i;
-      else f[i] = S::dec(sb[i * stride + m]);
+      else f[i] = (R)S::dec(sb[i * stride + m]);
     }
   }
   if (inlet) {
@@ -222,7 +222,8 @@ __device__ void gather_pre(const InstDev& I, const typename Store<ST>::T* sb, co
     inflow_velocity(I, y, z, t1, ud);
     R rt = R(0), uu[3];
     uint32_t m;
-    if (resolve_nb(I, x, y, z, 1, 0, 0, m) && !(fl && (fl[m] & FLAG_SOLID))) lagged<Q, ST>(sb, stride, m, rt, uu);
+    if (resolve_nb(I, x, y, z, 1, 0, 0, m) && !(fl && (fl[m] & FLAG_SOLID)))
+      lagged<Q, ST, R>(sb, stride, m, rt, uu);
     const R ui[3] = {(R)ud[0], (R)ud[1], (R)ud[2]};
     feq_dev<Q, R>(rt, ui, f);
     return;
@@ -231,7 +232,8 @@ __device__ void gather_pre(const InstDev& I, const typename Store<ST>::T* sb, co
     // Equilibrium at density 1 and the lagged velocity of x - e_x.
     R rt = R(0), uo[3] = {R(0), R(0), R(0)};
     uint32_t m;
-    if (resolve_nb(I, x, y, z, -1, 0, 0, m) && !(fl && (fl[m] & FLAG_SOLID))) lagged<Q, ST>(sb, stride, m, rt, uo);
+    if (resolve_nb(I, x, y, z, -1, 0, 0, m) && !(fl && (fl[m] & FLAG_SOLID)))
+      lagged<Q, ST, R>(sb, stride, m, rt, uo);
     feq_dev<Q, R>(R(0), uo, f);
     return;
   }
@@ -256,7 +258,7 @@ __device__ void gather_pre(const InstDev& I, const typename Store<ST>::T* sb, co
   };
   const uint32_t me = node_index(I, x, y, z);
   R rt_x, u_x[3];
-  lagged<Q, ST>(sb, stride, me, rt_x, u_x);
+  lagged<Q, ST, R>(sb, stride, me, rt_x, u_x);
   const R rho_n = R(1) + rt_x;
 
   // Target density: bounce-back-implied density plus the wall-motion term.
@@ -269,7 +271,7 @@ __device__ void gather_pre(const InstDev& I, const typename Store<ST>::T* sb, co
       R q, uw[3];
       link(i, q, uw);
       const R cu = R(cx(i)) * uw[0] + R(cy(i)) * uw[1] + R(cz<Q>(i)) * uw[2];
-      rtt += S::dec(sb[(Q - 1 - i) * stride + me]) + R(6.0 * weight<Q>(i)) * rho_n * cu;
+      rtt += (R)S::dec(sb[(Q - 1 - i) * stride + me]) + R(6.0 * weight<Q>(i)) * rho_n * cu;
     }
   }
   const R rho_t = R(1) + rtt;
@@ -288,10 +290,10 @@ __device__ void gather_pre(const InstDev& I, const typename Store<ST>::T* sb, co
     R ui[3];
     if (fluid_at(cx(i), cy(i), cz<Q>(i), m1)) {
       R r1, u1[3];
-      lagged<Q, ST>(sb, stride, m1, r1, u1);
+      lagged<Q, ST, R>(sb, stride, m1, r1, u1);
       if (fluid_at(2 * cx(i), 2 * cy(i), 2 * cz<Q>(i), m2)) {
         R r2, u2[3];
-        lagged<Q, ST>(sb, stride, m2, r2, u2);
+        lagged<Q, ST, R>(sb, stride, m2, r2, u2);
         const R a0 = R(2) / ((R(1) + q) * (R(2) + q));
         const R a1 = R(2) * q / (R(1) + q);
         const R a2 = -q / (R(2) + q);
@@ -309,7 +311,8 @@ __device__ void gather_pre(const InstDev& I, const typename Store<ST>::T* sb, co
 
   // Velocity gradient G[a][b] = d u_a / d x_b: central differences of the
   // lagged velocity, the wall point on a cut side (quadratic through the wall
-  // point, x + e, x + 2e; linear if x + 2e is not fluid).
+  // point, x + e, x + 2e; linear if x + 2e is not fluid).  Only the lagged
+  // velocities the chosen difference uses are read.
   R G[3][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}, {R(0), R(0), R(0)}};
 #pragma unroll
   for (int b = 0; b < D; ++b) {
@@ -319,40 +322,68 @@ __device__ void gather_pre(const InstDev& I, const typename Store<ST>::T* sb, co
     const bool cut_p = (miss >> im) & 1u;
     const int eb[3] = {b == 0, b == 1, b == 2};
     uint32_t p1, p2, m1, m2;
-    R up1[3], up2[3], um1[3], um2[3], rr;
     const bool fp1 = fluid_at(eb[0], eb[1], eb[2], p1);
     const bool fp2 = fp1 && fluid_at(2 * eb[0], 2 * eb[1], 2 * eb[2], p2);
     const bool fm1 = fluid_at(-eb[0], -eb[1], -eb[2], m1);
     const bool fm2 = fm1 && fluid_at(-2 * eb[0], -2 * eb[1], -2 * eb[2], m2);
-    if (fp1) lagged<Q, ST>(sb, stride, p1, rr, up1);
-    if (fp2) lagged<Q, ST>(sb, stride, p2, rr, up2);
-    if (fm1) lagged<Q, ST>(sb, stride, m1, rr, um1);
-    if (fm2) lagged<Q, ST>(sb, stride, m2, rr, um2);
-    R qm = R(0), qp = R(0), wm[3] = {R(0), R(0), R(0)}, wp[3] = {R(0), R(0), R(0)};
-    if (cut_m) link(ip, qm, wm);
-    if (cut_p) link(im, qp, wp);
+    R v1[3] = {R(0), R(0), R(0)}, v2[3] = {R(0), R(0), R(0)}, rr;
+    R qq = R(0), w[3] = {R(0), R(0), R(0)};
+    int form = 0;   // 0 none, 1 both cut, 2/3 quadratic/linear through the lower
+                    // wall, 4/5 through the upper wall, 6 central, 7/8 one-sided
+    if (cut_m && cut_p) {
+      R qm, wm[3], qp, wp[3];
+      link(ip, qm, wm);
+      link(im, qp, wp);
+      for (int a = 0; a < D; ++a) G[a][b] = (wp[a] - wm[a]) / (qp + qm);
+      continue;
+    } else if (cut_m) {
+      link(ip, qq, w);
+      if (fp2) {
+        lagged<Q, ST, R>(sb, stride, p1, rr, v1);
+        lagged<Q, ST, R>(sb, stride, p2, rr, v2);
+        form = 2;
+      } else if (fp1) {
+        lagged<Q, ST, R>(sb, stride, p1, rr, v1);
+        form = 3;
+      }
+    } else if (cut_p) {
+      link(im, qq, w);
+      if (fm2) {
+        lagged<Q, ST, R>(sb, stride, m1, rr, v1);
+        lagged<Q, ST, R>(sb, stride, m2, rr, v2);
+        form = 4;
+      } else if (fm1) {
+        lagged<Q, ST, R>(sb, stride, m1, rr, v1);
+        form = 5;
+      }
+    } else if (fp1 && fm1) {
+      lagged<Q, ST, R>(sb, stride, p1, rr, v1);
+      lagged<Q, ST, R>(sb, stride, m1, rr, v2);
+      form = 6;
+    } else if (fp1) {
+      lagged<Q, ST, R>(sb, stride, p1, rr, v1);
+      form = 7;
+    } else if (fm1) {
+      lagged<Q, ST, R>(sb, stride, m1, rr, v1);
+      form = 8;
+    }
     for (int a = 0; a < D; ++a) {
       R g = R(0);
-      if (cut_m && cut_p) {
-        g = (wp[a] - wm[a]) / (qp + qm);
-      } else if (cut_m) {
-        if (fp2)
-          g = R(-3) * wm[a] / ((R(1) + qm) * (R(2) + qm)) + up1[a] * (R(2) - qm) / (R(1) + qm) +
-              up2[a] * (qm - R(1)) / (R(2) + qm);
-        else if (fp1)
-          g = (up1[a] - wm[a]) / (R(1) + qm);
-      } else if (cut_p) {
-        if (fm2)
-          g = R(3) * wp[a] / ((R(1) + qp) * (R(2) + qp)) - um1[a] * (R(2) - qp) / (R(1) + qp) -
-              um2[a] * (qp - R(1)) / (R(2) + qp);
-        else if (fm1)
-          g = (wp[a] - um1[a]) / (R(1) + qp);
-      } else if (fp1 && fm1) {
-        g = R(0.5) * (up1[a] - um1[a]);
-      } else if (fp1) {
-        g = up1[a] - u_x[a];
-      } else if (fm1) {
-        g = u_x[a] - um1[a];
+      switch (form) {
+        case 2:
+          g = R(-3) * w[a] / ((R(1) + qq) * (R(2) + qq)) + v1[a] * (R(2) - qq) / (R(1) + qq) +
+              v2[a] * (qq - R(1)) / (R(2) + qq);
+          break;
+        case 3: g = (v1[a] - w[a]) / (R(1) + qq); break;
+        case 4:
+          g = R(3) * w[a] / ((R(1) + qq) * (R(2) + qq)) - v1[a] * (R(2) - qq) / (R(1) + qq) -
+              v2[a] * (qq - R(1)) / (R(2) + qq);
+          break;
+        case 5: g = (w[a] - v1[a]) / (R(1) + qq); break;
+        case 6: g = R(0.5) * (v1[a] - v2[a]); break;
+        case 7: g = v1[a] - u_x[a]; break;
+        case 8: g = u_x[a] - v1[a]; break;
+        default: break;
       }
       G[a][b] = g;
     }
@@ -403,6 +434,56 @@ __device__ void block_stats(float gmin, float gmax, double gsum, uint32_t cnt, u
 }
 
 // ---------------------------------------------------------------------------
+// Inflow / outflow plane node, computed inside the bulk kernel in its
+// arithmetic type R (Sec. III.A.1 inflow with its smooth ramp): every
+// population is the entropic equilibrium at the inflow velocity and the
+// lagged density of x + e_x, or at density 1 and the lagged velocity of
+// x - e_x, all in R (the inflow profile and ramp too).  Its density and
+// momentum are exactly those of the state, so
+// Delta = 0 and the collision (KBC or LBGK) is the identity (gamma = 2 by the
+// <Dh|Dh> = 0 rule): the kernel stores it without colliding.  Takes the
+// stored populations of that neighbour on entry (f; the bulk kernel pulls
+// them in place of the node's own sources), nb_fluid whether it is fluid;
+// ramp is the inflow ramp factor at the new time.  f receives the state
+// (deviations).
+// Returns false if the state is not valid (rho <= 0 or |u_a| >= 1).
+// ---------------------------------------------------------------------------
+template <int Q, typename R>
+__device__ __forceinline__ bool face_state(const InstDev& I, int y, int z, bool inlet,
+                                           bool nb_fluid, R ramp, R (&f)[Q]) {
+  R rt = R(0), u[3] = {R(0), R(0), R(0)};
+  if (nb_fluid) {
+    R r, j[3];
+    moments_dev<Q>(f, r, j);
+    if (inlet) {
+      rt = r;
+    } else {
+      const R ir = R(1) / (R(1) + r);
+      u[0] = j[0] * ir;
+      u[1] = j[1] * ir;
+      u[2] = j[2] * ir;
+    }
+  }
+  if (inlet) {
+    // Parabolic profile 1.5 U y(H - y)/(H/2)^2 (per axis), times the ramp.
+    R prof = ramp;
+    if (I.inlet_profile == 1) {
+      const R yp = R(y) + R(0.5), H = R(I.ny);
+      prof *= R(6) * yp * (H - yp) / (H * H);
+      if (I.D == 3) {
+        const R zp = R(z) + R(0.5), Z = R(I.nz);
+        prof *= R(6) * zp * (Z - zp) / (Z * Z);
+      }
+    }
+    for (int a = 0; a < 3; ++a) u[a] = R(I.u_in[a]) * prof;
+  }
+  const bool ok = R(1) + rt > R(0) && u[0] < R(1) && u[0] > R(-1) && u[1] < R(1) &&
+                  u[1] > R(-1) && u[2] < R(1) && u[2] > R(-1);
+  feq_dev<Q, R>(rt, u, f);
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
 // Bulk kernel: fused pull-stream + collide, one thread per node.
 // ---------------------------------------------------------------------------
 // MEM bit 0: non-temporal stores; bit 1: non-temporal loads; bit 2: 32-bit
@@ -433,7 +514,7 @@ __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_
 // Buffer resource word 3 for gfx9-family targets (raw, untyped 32-bit data).
 constexpr int kBufferWord3 = 0x00020000;
 
-template <int Q, int ST, int BLOCK, int WAVES, int MEM, bool STATS>
+template <int Q, int ST, int BLOCK, int WAVES, int MEM, bool STATS, bool FACES>
 __global__ void __launch_bounds__(BLOCK, WAVES)
     k_bulk(StepBuffers b, const Tile* __restrict__ tiles, int tile0) {
   using S = Store<ST>;
@@ -465,113 +546,166 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
   float gmin = 1e30f, gmax = -1e30f;
   double gsum = 0.0;
   uint32_t cnt = 0, f64 = 0;
-  for (int k = threadIdx.x; k < tl.count; k += BLOCK) {
-    const uint32_t node = (uint32_t)(tl.node0 + k);
-    // The flag is loaded with the pulls and tested after them, so that it
-    // adds no memory latency of its own; the pulls of a special node wrap
-    // periodically like any other and stay inside the instance.  The load is
-    // the aligned 32-bit word holding the node's flag byte (flag slices are
-    // padded to 256 bytes); without flags it reads the pool's first word and
-    // the mask is zero, so there is no branch before the pulls.
-    uint32_t fw = *reinterpret_cast<const uint32_t*>(fl ? fl + (node & ~3u) : b.flags);
-    const uint32_t fshift = (node & 3u) * 8u;
-    const Coord c = node_coord(I, node);
-    // Source of population i is node - c_i, wrapped periodically: per axis
-    // the node offset of the neighbour at -1 (dm) and +1 (dp), modulo 2^32,
-    // chosen between two per-instance constants (no per-node products).
-    const uint32_t dm[3] = {c.x == 0 ? wx : 0u - 1u, c.y == 0 ? wy : 0u - sy,
-                            c.z == 0 ? wz : 0u - sz};
-    const uint32_t dp[3] = {c.x == nx - 1 ? 0u - wx : 1u, c.y == ny - 1 ? 0u - wy : sy,
-                            c.z == nz - 1 ? 0u - wz : sz};
-    // Node offset of the source of (cx, cy, cz): the -c part of each axis.
-    auto dof = [&](int a, int ci) -> uint32_t { return ci == 0 ? 0u : (ci > 0 ? dm[a] : dp[a]); };
-    T raw[Q];
-    constexpr bool BUF = (MEM & 8) && sizeof(T) <= 4;
-    constexpr uint32_t es = sizeof(T);
-    const uint32_t pbytes = (uint32_t)stride * es;
-    if constexpr (BUF || (MEM & 4)) {
-      // Byte offsets within the instance's populations: the (cy, cz) part is
-      // formed once per pair, then each x neighbour adds its own.
-      const uint32_t base = node * es;
-      uint32_t yz[3][3];
+  // FACES: inflow ramp factor at the new time, formed once per thread.
+  R ramp = R(1);
+  if constexpr (FACES) {
+    if (I.face[0] == LBM_FACE_INLET && I.ramp_steps > 0) {
+      const double tt = fmin((double)(*b.clock + 1), (double)I.ramp_steps);
+      ramp = (R)(0.5 * (1.0 - cos(M_PI * tt / I.ramp_steps)));
+    }
+  }
+  // NPI nodes per thread and iteration (lanes on consecutive nodes, the
+  // second node BLOCK further on): all their pulls are issued before any is
+  // used.  D2Q9 moves only 9 values per node, so one node per wave in flight
+  // keeps too little memory traffic outstanding; D3Q27 keeps one.
+  constexpr int NPI = Q == 9 ? 2 : 1;
+  constexpr bool BUF = (MEM & 8) && sizeof(T) <= 4;
+  constexpr uint32_t es = sizeof(T);
+  const uint32_t pbytes = (uint32_t)stride * es;
+  for (int k0 = threadIdx.x; k0 < tl.count; k0 += BLOCK * NPI) {
+    T raw[NPI][Q];
+    uint32_t fw[NPI], node[NPI];
+    bool valid[NPI], face[NPI], inl[NPI];
+    uint32_t fdir[NPI];
+    int cy_[NPI], cz_[NPI];
 #pragma unroll
-      for (int jy = -1; jy <= 1; ++jy)
+    for (int n = 0; n < NPI; ++n) {
+      const int k = k0 + n * BLOCK;
+      valid[n] = k < tl.count;
+      // A lane without a second node loads the first node's sources again.
+      node[n] = (uint32_t)(tl.node0 + (valid[n] ? k : k0));
+      // The flag is loaded with the pulls and tested after them, so that it
+      // adds no memory latency of its own; the pulls of a special node wrap
+      // periodically like any other and stay inside the instance.  The load
+      // is the aligned 32-bit word holding the node's flag byte (flag slices
+      // are padded to 256 bytes); without flags it reads the pool's first
+      // word and the mask is zero, so there is no branch before the pulls.
+      fw[n] = *reinterpret_cast<const uint32_t*>(fl ? fl + (node[n] & ~3u) : b.flags);
+      const Coord c = node_coord(I, node[n]);
+      cy_[n] = c.y;
+      cz_[n] = c.z;
+      // Source of population i is node - c_i, wrapped periodically: per axis
+      // the node offset of the neighbour at -1 (dm) and +1 (dp), modulo 2^32,
+      // chosen between two per-instance constants (no per-node products).
+      const uint32_t dm[3] = {c.x == 0 ? wx : 0u - 1u, c.y == 0 ? wy : 0u - sy,
+                              c.z == 0 ? wz : 0u - sz};
+      const uint32_t dp[3] = {c.x == nx - 1 ? 0u - wx : 1u, c.y == ny - 1 ? 0u - wy : sy,
+                              c.z == nz - 1 ? 0u - wz : sz};
+      // Node offset of the source of (cx, cy, cz): the -c part of each axis.
+      auto dof = [&](int a, int ci) -> uint32_t { return ci == 0 ? 0u : (ci > 0 ? dm[a] : dp[a]); };
+      // FACES: an inflow (outflow) plane node pulls every population of
+      // x + e_x (x - e_x) instead, from which it forms its face equilibrium.
+      face[n] = false;
+      inl[n] = false;
+      fdir[n] = 0u;
+      if constexpr (FACES) {
+        inl[n] = I.face[0] == LBM_FACE_INLET && c.x == 0;
+        face[n] = inl[n] || (I.face[1] == LBM_FACE_OUTLET && c.x == nx - 1);
+        fdir[n] = inl[n] ? 1u : 0u - 1u;
+      }
+      if constexpr (BUF || (MEM & 4)) {
+        // Byte offsets within the instance's populations: the (cy, cz) part
+        // is formed once per pair, then each x neighbour adds its own.
+        const uint32_t base = node[n] * es;
+        uint32_t yz[3][3];
 #pragma unroll
-        for (int jz = -1; jz <= 1; ++jz)
-          yz[jy + 1][jz + 1] = base + (dof(1, jy) + (Q == 27 ? dof(2, jz) : 0u)) * es;
-      const uint32_t xb[3] = {dp[0] * es, 0u, dm[0] * es};   // by cx + 1
-      if constexpr (BUF) {
-        // Node part in the vector offset, population part (i * stride) in
-        // the scalar offset.
-        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<T*>(sb), (short)0, (int)(uint32_t)(Q * pbytes), kBufferWord3);
+        for (int jy = -1; jy <= 1; ++jy)
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-          raw[i] = buf_load<T, (MEM & 2) ? 2 : 0>(
-              rs, yz[cy(i) + 1][cz<Q>(i) + 1] + xb[cx(i) + 1], (uint32_t)i * pbytes);
+          for (int jz = -1; jz <= 1; ++jz)
+            yz[jy + 1][jz + 1] =
+                face[n] ? base : base + (dof(1, jy) + (Q == 27 ? dof(2, jz) : 0u)) * es;
+        const uint32_t xf = fdir[n] * es;
+        const uint32_t xb[3] = {face[n] ? xf : dp[0] * es, face[n] ? xf : 0u,
+                                face[n] ? xf : dm[0] * es};   // by cx + 1
+        if constexpr (BUF) {
+          // Node part in the vector offset, population part (i * stride) in
+          // the scalar offset.
+          const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+              const_cast<T*>(sb), (short)0, (int)(uint32_t)(Q * pbytes), kBufferWord3);
+#pragma unroll
+          for (int i = 0; i < Q; ++i)
+            raw[n][i] = buf_load<T, (MEM & 2) ? 2 : 0>(
+                rs, yz[cy(i) + 1][cz<Q>(i) + 1] + xb[cx(i) + 1], (uint32_t)i * pbytes);
+        } else {
+#pragma unroll
+          for (int i = 0; i < Q; ++i) {
+            const uint32_t off =
+                (uint32_t)i * pbytes + yz[cy(i) + 1][cz<Q>(i) + 1] + xb[cx(i) + 1];
+            const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(sb) + off);
+            raw[n][i] = (MEM & 2) ? __builtin_nontemporal_load(p) : *p;
+          }
+        }
       } else {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          const uint32_t off = (uint32_t)i * pbytes + yz[cy(i) + 1][cz<Q>(i) + 1] + xb[cx(i) + 1];
-          const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(sb) + off);
-          raw[i] = (MEM & 2) ? __builtin_nontemporal_load(p) : *p;
+          const uint32_t src =
+              face[n] ? node[n] + fdir[n]
+                      : node[n] + dof(0, cx(i)) + dof(1, cy(i)) + (Q == 27 ? dof(2, cz<Q>(i)) : 0u);
+          const T* p = sb + (i * stride + src);
+          raw[n][i] = (MEM & 2) ? __builtin_nontemporal_load(p) : *p;
         }
       }
-    } else {
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const uint32_t src = node + dof(0, cx(i)) + dof(1, cy(i)) + (Q == 27 ? dof(2, cz<Q>(i)) : 0u);
-        const T* p = sb + (i * stride + src);
-        raw[i] = (MEM & 2) ? __builtin_nontemporal_load(p) : *p;
-      }
     }
-    // All Q loads are issued before the first use: without this fence the
+    // All pulls are issued before the first use: without this fence the
     // scheduler consumes each value right after its load and a wave keeps a
     // single load in flight.
     __builtin_amdgcn_sched_barrier(0);
-    // An empty statement that the compiler must assume changes fw: the test
-    // cannot be moved above it, to right after the flag load.
-    asm volatile("" : "+v"(fw));
-    if ((fw >> fshift) & fmask) continue;
-    R f[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = S::dec(raw[i]);
-    CollideOut co;
-    if (!collide<Q, R, true>(f, P, co)) atomicOr(b.err, 1u);
-    if constexpr (BUF) {
-      const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
-          db, (short)0, (int)(uint32_t)(Q * pbytes), kBufferWord3);
+    for (int n = 0; n < NPI; ++n) {
+      // An empty statement that the compiler must assume changes fw: the
+      // test cannot be moved above it, to right after the flag load.
+      asm volatile("" : "+v"(fw[n]));
+      const uint32_t fshift = (node[n] & 3u) * 8u;
+      if (!valid[n] || ((fw[n] >> fshift) & (face[n] ? uint32_t(FLAG_SOLID) : fmask))) continue;
+      R f[Q];
 #pragma unroll
-      for (int i = 0; i < Q; ++i)
-        buf_store<T, (MEM & 1) ? 2 : 0>(S::enc(f[i]), rd, node * es, (uint32_t)i * pbytes);
-    } else {
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        T* p = (MEM & 4) ? reinterpret_cast<T*>(reinterpret_cast<char*>(db) +
-                                                  ((uint32_t)i * (uint32_t)stride + node) *
-                                                      (uint32_t)sizeof(T))
-                         : db + (i * stride + node);
-        if (MEM & 1) __builtin_nontemporal_store(S::enc(f[i]), p); else *p = S::enc(f[i]);
+      for (int i = 0; i < Q; ++i) f[i] = S::dec(raw[n][i]);
+      CollideOut co;
+      bool ok;
+      if (FACES && face[n]) {
+        ok = face_state<Q, R>(I, cy_[n], cz_[n], inl[n], !(fl[node[n] + fdir[n]] & FLAG_SOLID),
+                              ramp, f);
+        co.gamma = 2.0f;
+        co.fp64 = 0;
+      } else {
+        ok = collide<Q, R, true>(f, P, co);
       }
-    }
-    // Near-equilibrium nodes go to the FP64 pass; one atomic per wave.
-    const uint64_t m = __ballot(co.fp64 != 0);
-    if (m) {
-      const int lane = threadIdx.x & 63;
-      const int leader = __ffsll((unsigned long long)m) - 1;
-      uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(b.neq_count, (uint32_t)__popcll(m));
-      base = __shfl(base, leader);
-      if (co.fp64) {
-        const uint32_t slot = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-        if (slot < b.neq_cap) b.neq_list[slot] = make_uint2((uint32_t)tl.inst, node);
+      if (!ok) atomicOr(b.err, 1u);
+      if constexpr (BUF) {
+        const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+            db, (short)0, (int)(uint32_t)(Q * pbytes), kBufferWord3);
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          buf_store<T, (MEM & 1) ? 2 : 0>(S::enc(f[i]), rd, node[n] * es, (uint32_t)i * pbytes);
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          T* p = (MEM & 4) ? reinterpret_cast<T*>(reinterpret_cast<char*>(db) +
+                                                    ((uint32_t)i * (uint32_t)stride + node[n]) *
+                                                        (uint32_t)sizeof(T))
+                           : db + (i * stride + node[n]);
+          if (MEM & 1) __builtin_nontemporal_store(S::enc(f[i]), p); else *p = S::enc(f[i]);
+        }
       }
-    }
-    if (STATS && !co.fp64) {
-      gmin = fminf(gmin, co.gamma);
-      gmax = fmaxf(gmax, co.gamma);
-      gsum += co.gamma;
-      cnt += 1;
+      // Near-equilibrium nodes go to the FP64 pass; one atomic per wave.
+      const uint64_t m = __ballot(co.fp64 != 0);
+      if (m) {
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(b.neq_count, (uint32_t)__popcll(m));
+        base = __shfl(base, leader);
+        if (co.fp64) {
+          const uint32_t slot = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+          if (slot < b.neq_cap) b.neq_list[slot] = make_uint2((uint32_t)tl.inst, node[n]);
+        }
+      }
+      if (STATS && !co.fp64) {
+        gmin = fminf(gmin, co.gamma);
+        gmax = fmaxf(gmax, co.gamma);
+        gsum += co.gamma;
+        cnt += 1;
+      }
     }
   }
   if (STATS) block_stats<BLOCK>(gmin, gmax, gsum, cnt, f64, b.stats + ti);
@@ -599,12 +733,13 @@ __device__ __forceinline__ bool in_region(const Region& rg, int x, int y, int z)
          z < rg.hi[2];
 }
 
-// Boundary node lists: the special nodes (face planes, cut links) of the
-// scanned regions, each once (a node inside an earlier region of its instance
+// Boundary node lists: the nodes with missing populations of the scanned
+// regions, each once (a node inside an earlier region of its instance
 // belongs to that region's tiles), as (instance, node) pairs appended with one
-// atomic per wave.  Nodes on an inflow or outflow plane go to list[cap + ...]
-// (count[1]); the others, whose missing populations Grad's approximation
-// fills, to list[...] (count[0]).
+// atomic per list and workgroup.  Nodes with a cut link to a body go to
+// list[...] (count[0], one wavefront each); nodes whose missing populations
+// all come from wall faces go to list[cap + ...] (count[1], one thread each).
+// Inflow and outflow plane nodes are left to the bulk kernel.
 template <int Q>
 __global__ void __launch_bounds__(256) k_boundary_scan(const InstDev* __restrict__ insts,
                                                        const Region* __restrict__ regions,
@@ -615,7 +750,7 @@ __global__ void __launch_bounds__(256) k_boundary_scan(const InstDev* __restrict
   const Region rg = regions[bt.region];
   const InstDev& I = insts[rg.inst];
   const int k = threadIdx.x;
-  bool take = false, face = false;
+  bool take = false, body = false;
   uint32_t node = 0;
   int x, y, z;
   if (k < bt.count && I.flag_off >= 0 && box_local(rg, bt.local0 + k, x, y, z)) {
@@ -624,10 +759,12 @@ __global__ void __launch_bounds__(256) k_boundary_scan(const InstDev* __restrict
       if (in_region(regions[r], x, y, z)) owned = false;
     node = node_index(I, x, y, z);
     const uint8_t fv = flags[I.flag_off + node];
-    take = owned && !(fv & FLAG_SOLID) && (fv & (FLAG_STATIC | FLAG_BODY));
-    face = (x == 0 && I.face[0] == LBM_FACE_INLET) || (x == I.nx - 1 && I.face[1] == LBM_FACE_OUTLET);
+    const bool face = (x == 0 && I.face[0] == LBM_FACE_INLET) ||
+                      (x == I.nx - 1 && I.face[1] == LBM_FACE_OUTLET);
+    take = owned && !face && !(fv & FLAG_SOLID) && (fv & (FLAG_STATIC | FLAG_BODY));
+    body = (fv & FLAG_BODY) != 0;
   }
-  // One atomic per list and workgroup (not per wave): every wave of a face
+  // One atomic per list and workgroup (not per wave): every wave of a wall
   // plane has nodes to append, and same-address atomics serialise.
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   __shared__ uint32_t s_cnt[2][4];
@@ -635,7 +772,7 @@ __global__ void __launch_bounds__(256) k_boundary_scan(const InstDev* __restrict
   uint64_t m[2];
 #pragma unroll
   for (int which = 0; which < 2; ++which) {
-    m[which] = __ballot(take && (face == (which == 1)));
+    m[which] = __ballot(take && (body == (which == 0)));
     if (lane == 0) s_cnt[which][wv] = (uint32_t)__popcll(m[which]);
   }
   __syncthreads();
@@ -647,7 +784,7 @@ __global__ void __launch_bounds__(256) k_boundary_scan(const InstDev* __restrict
   __syncthreads();
 #pragma unroll
   for (int which = 0; which < 2; ++which) {
-    if (take && (face == (which == 1))) {
+    if (take && (body == (which == 0))) {
       uint32_t slot = s_base[which] + (uint32_t)__popcll(m[which] & ((1ull << lane) - 1ull));
       for (int w = 0; w < wv; ++w) slot += s_cnt[which][w];
       if (slot < cap) list[which * cap + slot] = make_uint2((uint32_t)rg.inst, node);
@@ -655,12 +792,14 @@ __global__ void __launch_bounds__(256) k_boundary_scan(const InstDev* __restrict
   }
 }
 
-// Inflow / outflow plane nodes, one thread per node (Sec. III.A.1 inflow
-// with its ramp): equilibrium at the inflow velocity and the lagged density of
-// x + e_x, or at density 1 and the lagged velocity of x - e_x, formed in FP64;
-// its collision is the identity (see below).
+// Nodes whose missing populations all come from wall faces (resting walls
+// half a spacing outside the face, q = 1/2), one thread each: the
+// pre-collision state with Grad's approximation for the missing populations
+// (Sec. II.C.1) and the KBC collision (Eqs. 1-6), both in FP64 whatever the
+// storage form, as for the other boundary nodes.  Consecutive list entries
+// are mostly consecutive nodes of a wall row, so the loads coalesce.
 template <int Q, int ST>
-__global__ void __launch_bounds__(64) k_boundary_face(StepBuffers b, const uint2* __restrict__ list,
+__global__ void __launch_bounds__(64) k_boundary_wall(StepBuffers b, const uint2* __restrict__ list,
                                                      const uint32_t* __restrict__ count,
                                                      uint32_t cap, int stat0) {
   using S = Store<ST>;
@@ -677,48 +816,24 @@ __global__ void __launch_bounds__(64) k_boundary_face(StepBuffers b, const uint2
     T* db = static_cast<T*>(b.dst) + I.pop_off;
     const uint8_t* fl = b.flags + I.flag_off;
     const Coord c = node_coord(I, e.y);
-    const bool inlet = c.x == 0 && I.face[0] == LBM_FACE_INLET;
-    double rt = 0.0, u[3] = {0.0, 0.0, 0.0};
-    uint32_t m;
-    if (resolve_nb(I, c.x, c.y, c.z, inlet ? 1 : -1, 0, 0, m) && !(fl[m] & FLAG_SOLID)) {
-      double r = 0.0, j3[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-      for (int p = 0; p < Q; ++p) {
-        const double v = (double)S::dec(sb[p * I.stride + m]);
-        r += v;
-        if (cx(p) > 0) j3[0] += v;
-        if (cx(p) < 0) j3[0] -= v;
-        if (cy(p) > 0) j3[1] += v;
-        if (cy(p) < 0) j3[1] -= v;
-        if (cz<Q>(p) > 0) j3[2] += v;
-        if (cz<Q>(p) < 0) j3[2] -= v;
-      }
-      if (inlet) {
-        rt = r;
-      } else {
-        const double ir = 1.0 / (1.0 + r);
-        for (int a = 0; a < 3; ++a) u[a] = j3[a] * ir;
-      }
-    }
-    if (inlet) inflow_velocity(I, c.y, c.z, t1, u);
-    // Every population of a face node is the entropic equilibrium of (rho, u),
-    // whose density and momentum are exactly rho and rho u: Delta = 0, so the
-    // collision (KBC or LBGK) returns the state unchanged and gamma is 2 by
-    // the <Dh|Dh> = 0 rule.  The state is written as it is, after the same
-    // validity check the collision makes.
-    const bool ok = 1.0 + rt > 0.0 && fabs(u[0]) < 1.0 && fabs(u[1]) < 1.0 &&
-                    fabs(u[2]) < 1.0;
-    if (!ok) atomicOr(b.err, 1u);
     double f[Q];
-    feq_dev<Q, double>(rt, u, f);
+    gather_pre<Q, ST, double>(I, sb, fl, c.x, c.y, c.z, t1, f);
+    CollideParams<double> P;
+    P.beta = I.beta;
+    P.inv_beta = 1.0 / I.beta;
+    P.beta_d = I.beta;
+    P.lbgk = I.collision;
+    P.trace_in_s = I.trace_in_s;
+    P.near_eq = 0.0f;
+    CollideOut co;
+    if (!collide<Q, double, false>(f, P, co)) atomicOr(b.err, 1u);
 #pragma unroll
     for (int i = 0; i < Q; ++i) db[i * I.stride + e.y] = S::enc_d(f[i]);
-    if (ok) {
-      gmin = fminf(gmin, 2.0f);
-      gmax = fmaxf(gmax, 2.0f);
-      gsum += 2.0;
-      cnt += 1;
-    }
+    gmin = fminf(gmin, co.gamma);
+    gmax = fmaxf(gmax, co.gamma);
+    gsum += co.gamma;
+    cnt += 1;
+    f64 += 1;
   }
   if (b.stats) block_stats<64>(gmin, gmax, gsum, cnt, f64, b.stats + stat0 + blockIdx.x);
 }
@@ -772,8 +887,9 @@ __device__ __forceinline__ int lag_slot(int i, int k) {
 }
 
 // ---------------------------------------------------------------------------
-// Nodes with missing populations (walls, cut links), one group of GL lanes
-// per node (GL = 64 for D3Q27, 32 for D2Q9: two nodes per wavefront).
+// Nodes with a cut link to a body (and any wall links they have), one group
+// of GL lanes per node (GL = 64 for D3Q27, 32 for D2Q9: two nodes per
+// wavefront).
 // gather_pre above does the same work in one thread, reading the lagged
 // moments of up to 2(Q-1)+1 neighbours one after another; here the lanes take
 // them in parallel:
@@ -782,7 +898,9 @@ __device__ __forceinline__ int lag_slot(int i, int k) {
 //   lane l < 2(Q-1)+1     lagged (rho~, u) of x (l = 0) or x + k c_i where
 //                         Grad's target velocity or the velocity gradient
 //                         needs it;
-//   lane 0 of the group   Grad target values (Sec. II.C.1);
+//   lane i < Q            its term of the target density and, if missing,
+//                         its target velocity (group sums: rho_t, u_t);
+//   lane a + 3 b < 9      the target gradient entry G[a][b] (Sec. II.C.1);
 //   lane i < Q            f*_i for the missing i, then the KBC collision
 //                         (Eqs. 1-6) lane-parallel in FP64 with group sums,
 //                         and the store of population i.
@@ -804,7 +922,7 @@ __global__ void __launch_bounds__(64) k_boundary_wave(StepBuffers b, const uint2
   __shared__ double s_lr[NG][NS], s_lu[NG][NS][3];
   __shared__ int s_lf[NG][NS];
   __shared__ uint32_t s_miss[NG];
-  __shared__ double s_t[NG][10];   // rho_t, u_t[3], Pi[6]
+  __shared__ double s_G[NG][9];    // target velocity gradient G[a + 3 b]
   const int g = threadIdx.x / GL, lane = threadIdx.x % GL;
   const double t1 = (double)(*b.clock + 1);
   float gmin = 1e30f, gmax = -1e30f;
@@ -907,53 +1025,54 @@ __global__ void __launch_bounds__(64) k_boundary_wave(StepBuffers b, const uint2
       s_lf[g][lane] = fluid;
     }
     __syncthreads();
-    // ---- Grad target values (lane 0) ---------------------------------------
-    if (active && lane == 0 && miss) {
+    // ---- Grad target values (Sec. II.C.1), lane-parallel -------------------
+    // Lane i forms the target-density term and the target velocity of its
+    // own population (group sums give rho_t and u_t); lanes a + 3 b < 9 form
+    // the gradient entry G[a][b] = d u_a / d x_b.
+    const int i = lane;
+    const bool pop = active && i < Q;
+    const bool mi = pop && ((miss >> i) & 1u);
+    double tr = 0.0, v0 = 0.0, v1 = 0.0, v2 = 0.0;
+    if (mi) {
+      // Bounce-back-implied density plus the wall-motion term.
       const double rho_n = 1.0 + s_lr[g][0];
-      double rtt = 0.0;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        if (!((miss >> i) & 1u)) {
-          rtt += s_f[g][i];
-        } else {
-          const double cu = cx(i) * s_uw[g][i][0] + cy(i) * s_uw[g][i][1] + cz<Q>(i) * s_uw[g][i][2];
-          rtt += s_opp[g][i] + 6.0 * weight<Q>(i) * rho_n * cu;
-        }
+      const double w0 = s_uw[g][i][0], w1 = s_uw[g][i][1], w2 = s_uw[g][i][2];
+      tr = s_opp[g][i] + 6.0 * weight<Q>(i) * rho_n * (cx(i) * w0 + cy(i) * w1 + cz<Q>(i) * w2);
+      // Velocity at x interpolated along c_i through the wall point (s = -q)
+      // and the lagged velocities at x + c_i (s = 1), x + 2 c_i (s = 2).
+      const double q = s_q[g][i];
+      const int l1 = lag_slot<Q>(i, 1), l2 = lag_slot<Q>(i, 2);
+      if (s_lf[g][l1] && s_lf[g][l2]) {
+        const double a0 = 2.0 / ((1.0 + q) * (2.0 + q));
+        const double a1 = 2.0 * q / (1.0 + q);
+        const double a2 = -q / (2.0 + q);
+        v0 = a0 * w0 + a1 * s_lu[g][l1][0] + a2 * s_lu[g][l2][0];
+        v1 = a0 * w1 + a1 * s_lu[g][l1][1] + a2 * s_lu[g][l2][1];
+        v2 = a0 * w2 + a1 * s_lu[g][l1][2] + a2 * s_lu[g][l2][2];
+      } else if (s_lf[g][l1]) {
+        const double iq = 1.0 / (1.0 + q);
+        v0 = (w0 + q * s_lu[g][l1][0]) * iq;
+        v1 = (w1 + q * s_lu[g][l1][1]) * iq;
+        v2 = (w2 + q * s_lu[g][l1][2]) * iq;
+      } else {
+        v0 = w0;
+        v1 = w1;
+        v2 = w2;
       }
-      const double rho_t = 1.0 + rtt;
-      double ut0 = 0.0, ut1 = 0.0, ut2 = 0.0;
-      int nm = 0;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        if (!((miss >> i) & 1u)) continue;
-        const double q = s_q[g][i];
-        const int l1 = lag_slot<Q>(i, 1), l2 = lag_slot<Q>(i, 2);
-        const double w0 = s_uw[g][i][0], w1 = s_uw[g][i][1], w2 = s_uw[g][i][2];
-        if (s_lf[g][l1] && s_lf[g][l2]) {
-          const double a0 = 2.0 / ((1.0 + q) * (2.0 + q));
-          const double a1 = 2.0 * q / (1.0 + q);
-          const double a2 = -q / (2.0 + q);
-          ut0 += a0 * w0 + a1 * s_lu[g][l1][0] + a2 * s_lu[g][l2][0];
-          ut1 += a0 * w1 + a1 * s_lu[g][l1][1] + a2 * s_lu[g][l2][1];
-          ut2 += a0 * w2 + a1 * s_lu[g][l1][2] + a2 * s_lu[g][l2][2];
-        } else if (s_lf[g][l1]) {
-          ut0 += (w0 + q * s_lu[g][l1][0]) / (1.0 + q);
-          ut1 += (w1 + q * s_lu[g][l1][1]) / (1.0 + q);
-          ut2 += (w2 + q * s_lu[g][l1][2]) / (1.0 + q);
-        } else {
-          ut0 += w0;
-          ut1 += w1;
-          ut2 += w2;
-        }
-        ++nm;
-      }
-      ut0 /= nm;
-      ut1 /= nm;
-      ut2 /= nm;
-      // G[a][b] = d u_a / d x_b, as in gather_pre.
-      double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-#pragma unroll
-      for (int bb = 0; bb < D; ++bb) {
+    } else if (pop) {
+      tr = s_f[g][i];
+    }
+    const double rho_t = 1.0 + group_sum<GL>(tr);
+    const double nmi = miss ? 1.0 / (double)__popc(miss) : 0.0;
+    const double ut[3] = {group_sum<GL>(v0) * nmi, group_sum<GL>(v1) * nmi,
+                          group_sum<GL>(v2) * nmi};
+    // G[a][b]: central differences of the lagged velocity; on a cut side the
+    // quadratic through the wall point, x + e, x + 2 e (linear if x + 2 e is
+    // not fluid); both sides cut: across the two wall points.
+    if (active && lane < 9) {
+      const int a = lane % 3, bb = lane / 3;
+      double gr = 0.0;
+      if (miss && a < D && bb < D) {
         const int ip = axis_pop<Q>(bb, +1);   // c = +e_b: slots x + e_b, x + 2 e_b
         const int im = axis_pop<Q>(bb, -1);   // c = -e_b
         const bool cut_m = (miss >> ip) & 1u, cut_p = (miss >> im) & 1u;
@@ -961,62 +1080,50 @@ __global__ void __launch_bounds__(64) k_boundary_wave(StepBuffers b, const uint2
         const int m1 = lag_slot<Q>(im, 1), m2 = lag_slot<Q>(im, 2);
         const bool fp1 = s_lf[g][p1], fp2 = fp1 && s_lf[g][p2];
         const bool fm1 = s_lf[g][m1], fm2 = fm1 && s_lf[g][m2];
-        const double qm = cut_m ? s_q[g][ip] : 0.0, qp = cut_p ? s_q[g][im] : 0.0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          const double wm = cut_m ? s_uw[g][ip][a] : 0.0, wp = cut_p ? s_uw[g][im][a] : 0.0;
-          const double up1 = fp1 ? s_lu[g][p1][a] : 0.0, up2 = fp2 ? s_lu[g][p2][a] : 0.0;
-          const double um1 = fm1 ? s_lu[g][m1][a] : 0.0, um2 = fm2 ? s_lu[g][m2][a] : 0.0;
-          double gr = 0.0;
-          if (cut_m && cut_p) {
-            gr = (wp - wm) / (qp + qm);
-          } else if (cut_m) {
-            if (fp2)
-              gr = -3.0 * wm / ((1.0 + qm) * (2.0 + qm)) + up1 * (2.0 - qm) / (1.0 + qm) +
-                   up2 * (qm - 1.0) / (2.0 + qm);
-            else if (fp1)
-              gr = (up1 - wm) / (1.0 + qm);
-          } else if (cut_p) {
-            if (fm2)
-              gr = 3.0 * wp / ((1.0 + qp) * (2.0 + qp)) - um1 * (2.0 - qp) / (1.0 + qp) -
-                   um2 * (qp - 1.0) / (2.0 + qp);
-            else if (fm1)
-              gr = (wp - um1) / (1.0 + qp);
-          } else if (fp1 && fm1) {
-            gr = 0.5 * (up1 - um1);
-          } else if (fp1) {
-            gr = up1 - s_lu[g][0][a];
-          } else if (fm1) {
-            gr = s_lu[g][0][a] - um1;
-          }
-          G[a][bb] = gr;
+        if (cut_m && cut_p) {
+          gr = (s_uw[g][im][a] - s_uw[g][ip][a]) / (s_q[g][im] + s_q[g][ip]);
+        } else if (cut_m) {
+          const double qm = s_q[g][ip], wm = s_uw[g][ip][a];
+          if (fp2)
+            gr = -3.0 * wm / ((1.0 + qm) * (2.0 + qm)) + s_lu[g][p1][a] * (2.0 - qm) / (1.0 + qm) +
+                 s_lu[g][p2][a] * (qm - 1.0) / (2.0 + qm);
+          else if (fp1)
+            gr = (s_lu[g][p1][a] - wm) / (1.0 + qm);
+        } else if (cut_p) {
+          const double qp = s_q[g][im], wp = s_uw[g][im][a];
+          if (fm2)
+            gr = 3.0 * wp / ((1.0 + qp) * (2.0 + qp)) - s_lu[g][m1][a] * (2.0 - qp) / (1.0 + qp) -
+                 s_lu[g][m2][a] * (qp - 1.0) / (2.0 + qp);
+          else if (fm1)
+            gr = (wp - s_lu[g][m1][a]) / (1.0 + qp);
+        } else if (fp1 && fm1) {
+          gr = 0.5 * (s_lu[g][p1][a] - s_lu[g][m1][a]);
+        } else if (fp1) {
+          gr = s_lu[g][p1][a] - s_lu[g][0][a];
+        } else if (fm1) {
+          gr = s_lu[g][0][a] - s_lu[g][m1][a];
         }
       }
-      const double kneq = rho_t / (6.0 * I.beta);
-      s_t[g][0] = rho_t;
-      s_t[g][1] = ut0;
-      s_t[g][2] = ut1;
-      s_t[g][3] = ut2;
-      s_t[g][4] = rho_t / 3.0 + rho_t * ut0 * ut0 - kneq * 2.0 * G[0][0];
-      s_t[g][5] = rho_t / 3.0 + rho_t * ut1 * ut1 - kneq * 2.0 * G[1][1];
-      s_t[g][6] = rho_t / 3.0 + rho_t * ut2 * ut2 - kneq * 2.0 * G[2][2];
-      s_t[g][7] = rho_t * ut0 * ut1 - kneq * (G[0][1] + G[1][0]);
-      s_t[g][8] = rho_t * ut0 * ut2 - kneq * (G[0][2] + G[2][0]);
-      s_t[g][9] = rho_t * ut1 * ut2 - kneq * (G[1][2] + G[2][1]);
+      s_G[g][lane] = gr;
     }
     __syncthreads();
     // ---- f* for the missing populations, then the collision ----------------
-    const int i = lane;
+    // Pi = rho/3 I + rho u u - rho/(6 beta) (G + G^T)  (Pi^eq + Pi^neq, cs^2 = 1/3)
     double d = 0.0;
-    if (active && i < Q) {
+    if (pop) {
       d = s_f[g][i];
-      if ((miss >> i) & 1u) {
-        const double ut[3] = {s_t[g][1], s_t[g][2], s_t[g][3]};
-        const double Pi[6] = {s_t[g][4], s_t[g][5], s_t[g][6], s_t[g][7], s_t[g][8], s_t[g][9]};
-        d = grad_dev<Q, double>(i, s_t[g][0], ut, Pi);
+      if (mi) {
+        const double kneq = rho_t / (6.0 * I.beta);
+        const double (&G)[9] = s_G[g];   // G[a + 3 b]
+        const double Pi[6] = {rho_t / 3.0 + rho_t * ut[0] * ut[0] - kneq * 2.0 * G[0],
+                              rho_t / 3.0 + rho_t * ut[1] * ut[1] - kneq * 2.0 * G[4],
+                              rho_t / 3.0 + rho_t * ut[2] * ut[2] - kneq * 2.0 * G[8],
+                              rho_t * ut[0] * ut[1] - kneq * (G[3] + G[1]),
+                              rho_t * ut[0] * ut[2] - kneq * (G[6] + G[2]),
+                              rho_t * ut[1] * ut[2] - kneq * (G[7] + G[5])};
+        d = grad_dev<Q, double>(i, rho_t, ut, Pi);
       }
     }
-    const bool pop = active && i < Q;
     // Moments of the pre-collision state.
     const double rt = group_sum<GL>(pop ? d : 0.0);
     const double jx = group_sum<GL>(pop ? cx(i) * d : 0.0);
@@ -1126,12 +1233,15 @@ __global__ void __launch_bounds__(256) k_geometry(int stage, const InstDev* __re
   const uint32_t node = node_index(I, x, y, z);
   const uint8_t fv = fl[node];
   if (stage == 0) {
+    // Solid at the next time; a fresh node (solid now, fluid at the next
+    // time) is refilled with the equilibrium at the mean lagged density of
+    // the neighbours that are fluid now and the body velocity.  The refill
+    // reads only the FLAG_SOLID bits of the neighbours, which this stage
+    // does not change, and the populations of nodes that are fluid now,
+    // which it does not write.
     const bool in = body_inside(I, x, y, z, t);
     fl[node] = (uint8_t)((fv & ~FLAG_SOLID_NEXT) | (in ? FLAG_SOLID_NEXT : 0));
-  } else if (stage == 1) {
-    // Fresh node (solid now, fluid at the next time): equilibrium at the mean
-    // lagged density of neighbours that are fluid now and the body velocity.
-    if (!((fv & FLAG_SOLID) && !(fv & FLAG_SOLID_NEXT))) return;
+    if (!((fv & FLAG_SOLID) && !in)) return;
     T* sb = static_cast<T*>(src) + I.pop_off;
     R sum = R(0);
     int cnt = 0;
@@ -1142,7 +1252,7 @@ __global__ void __launch_bounds__(256) k_geometry(int stage, const InstDev* __re
       if (!resolve_nb(I, x, y, z, cx(i), cy(i), cz<Q>(i), m)) continue;
       if (fl[m] & FLAG_SOLID) continue;
       R rt, uu[3];
-      lagged<Q, ST>(sb, I.stride, m, rt, uu);
+      lagged<Q, ST, R>(sb, I.stride, m, rt, uu);
       sum += R(1) + rt;
       ++cnt;
     }
@@ -1273,6 +1383,30 @@ __global__ void k_decode(const InstDev* __restrict__ insts, int inst, int64_t N,
   for (int i = 0; i < Q; ++i) f[i * N + n] = weight<Q>(i) + (double)S::dec(sb[i * I.stride + n]);
 }
 
+// Populations of the box [lo, lo + ext) of one instance (box-local node
+// order x-fastest, population-major, full f_i in FP64); lo may be negative or
+// lo + ext exceed the size along periodic axes (wrapped once; the host
+// checks that).
+template <int Q, int ST>
+__global__ void k_decode_box(const InstDev* __restrict__ insts, int inst, int3 lo, int3 ext,
+                             const void* buf, double* __restrict__ f) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  const int64_t Nb = (int64_t)ext.x * ext.y * ext.z;
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= Nb) return;
+  const InstDev& I = insts[inst];
+  const int lx = (int)(n % ext.x), ly = (int)((n / ext.x) % ext.y), lz = (int)(n / ((int64_t)ext.x * ext.y));
+  int x = lo.x + lx, y = lo.y + ly, z = lo.z + lz;
+  x += x < 0 ? I.nx : (x >= I.nx ? -I.nx : 0);
+  y += y < 0 ? I.ny : (y >= I.ny ? -I.ny : 0);
+  z += z < 0 ? I.nz : (z >= I.nz ? -I.nz : 0);
+  const T* sb = static_cast<const T*>(buf) + I.pop_off;
+  const uint32_t m = node_index(I, x, y, z);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) f[i * Nb + n] = weight<Q>(i) + (double)S::dec(sb[i * I.stride + m]);
+}
+
 template <int Q, int ST>
 __global__ void k_encode(const InstDev* __restrict__ insts, int inst, int64_t N,
                          const double* __restrict__ f, void* buf) {
@@ -1345,32 +1479,35 @@ __global__ void __launch_bounds__(256) k_moments(const InstDev* __restrict__ ins
 // ---------------------------------------------------------------------------
 // Wall force (Sec. II.C.2).
 // ---------------------------------------------------------------------------
+// Pre-collision stress sigma = -p I - (1 - beta) Pi^(1) of node m in FP64
+// (Sec. II.C.2), Pi^(1) = sum_i (f_i - f^eq_i) c_i c_i, from the state the
+// last step streamed (sb) with the same boundary fill.  Order xx, yy, zz,
+// xy, xz, yz.
 template <int Q, int ST>
 __device__ void node_stress(const InstDev& I, const typename Store<ST>::T* sb, const uint8_t* fl,
                             uint32_t m, double t, double (&sig)[6]) {
-  using R = typename Store<ST>::R;
   const Coord c = node_coord(I, m);
-  R f[Q];
-  gather_pre<Q, ST>(I, sb, fl, c.x, c.y, c.z, t, f);
-  R rt, j[3];
+  double f[Q];
+  gather_pre<Q, ST, double>(I, sb, fl, c.x, c.y, c.z, t, f);
+  double rt, j[3];
   moments_dev<Q>(f, rt, j);
-  const R rho = R(1) + rt;
-  const R u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
-  R fe[Q];
-  feq_dev<Q, R>(rt, u, fe);
-  R P[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+  const double rho = 1.0 + rt;
+  const double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+  double fe[Q];
+  feq_dev<Q, double>(rt, u, fe);
+  double P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const R dl = f[i] - fe[i];
-    P[0] += R(cx(i) * cx(i)) * dl;
-    P[1] += R(cy(i) * cy(i)) * dl;
-    P[2] += R(cz<Q>(i) * cz<Q>(i)) * dl;
-    P[3] += R(cx(i) * cy(i)) * dl;
-    P[4] += R(cx(i) * cz<Q>(i)) * dl;
-    P[5] += R(cy(i) * cz<Q>(i)) * dl;
+    const double dl = f[i] - fe[i];
+    P[0] += (double)(cx(i) * cx(i)) * dl;
+    P[1] += (double)(cy(i) * cy(i)) * dl;
+    P[2] += (double)(cz<Q>(i) * cz<Q>(i)) * dl;
+    P[3] += (double)(cx(i) * cy(i)) * dl;
+    P[4] += (double)(cx(i) * cz<Q>(i)) * dl;
+    P[5] += (double)(cy(i) * cz<Q>(i)) * dl;
   }
-  const double k = 1.0 - I.beta, p = (double)rho / 3.0;
-  for (int e = 0; e < 6; ++e) sig[e] = -k * (double)P[e] - (e < 3 ? p : 0.0);
+  const double k = 1.0 - I.beta, p = rho / 3.0;
+  for (int e = 0; e < 6; ++e) sig[e] = -k * P[e] - (e < 3 ? p : 0.0);
   if (dims<Q>() == 2) sig[2] = sig[4] = sig[5] = 0.0;
 }
 
@@ -1566,55 +1703,66 @@ bool bulk_variant_off32(int v) { return (kVariants[(v >= 0 && v < kNumVariants) 
 
 template <int Q, int ST, int BLOCK, int WAVES, int MEM>
 static hipError_t launch_bulk_v(const StepBuffers& b, const Tile* tiles, int tile0, int ntiles,
-                                hipStream_t s) {
+                                bool faces, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (b.stats)
-    hipLaunchKernelGGL((k_bulk<Q, ST, BLOCK, WAVES, MEM, true>), dim3(ntiles), dim3(BLOCK), 0, s,
-                       b, tiles, tile0);
-  else
-    hipLaunchKernelGGL((k_bulk<Q, ST, BLOCK, WAVES, MEM, false>), dim3(ntiles), dim3(BLOCK), 0, s,
-                       b, tiles, tile0);
+  if (b.stats) {
+    if (faces)
+      hipLaunchKernelGGL((k_bulk<Q, ST, BLOCK, WAVES, MEM, true, true>), dim3(ntiles), dim3(BLOCK),
+                         0, s, b, tiles, tile0);
+    else
+      hipLaunchKernelGGL((k_bulk<Q, ST, BLOCK, WAVES, MEM, true, false>), dim3(ntiles),
+                         dim3(BLOCK), 0, s, b, tiles, tile0);
+  } else {
+    if (faces)
+      hipLaunchKernelGGL((k_bulk<Q, ST, BLOCK, WAVES, MEM, false, true>), dim3(ntiles),
+                         dim3(BLOCK), 0, s, b, tiles, tile0);
+    else
+      hipLaunchKernelGGL((k_bulk<Q, ST, BLOCK, WAVES, MEM, false, false>), dim3(ntiles),
+                         dim3(BLOCK), 0, s, b, tiles, tile0);
+  }
   return hipGetLastError();
 }
 
 template <int Q, int ST>
 static hipError_t launch_bulk(int v, const StepBuffers& b, const Tile* tiles, int tile0,
-                              int ntiles, hipStream_t s) {
+                              int ntiles, bool faces, hipStream_t s) {
   switch (v) {
-    case 1: return launch_bulk_v<Q, ST, 256, 1, 0>(b, tiles, tile0, ntiles, s);
-    case 2: return launch_bulk_v<Q, ST, 128, 1, 0>(b, tiles, tile0, ntiles, s);
-    case 3: return launch_bulk_v<Q, ST, 512, 1, 0>(b, tiles, tile0, ntiles, s);
-    case 4: return launch_bulk_v<Q, ST, 256, 2, 0>(b, tiles, tile0, ntiles, s);
-    case 5: return launch_bulk_v<Q, ST, 256, 2, 0>(b, tiles, tile0, ntiles, s);
-    case 6: return launch_bulk_v<Q, ST, 512, 1, 1>(b, tiles, tile0, ntiles, s);
-    case 7: return launch_bulk_v<Q, ST, 256, 2, 1>(b, tiles, tile0, ntiles, s);
-    case 8: return launch_bulk_v<Q, ST, 256, 2, 1>(b, tiles, tile0, ntiles, s);
-    case 9: return launch_bulk_v<Q, ST, 512, 1, 3>(b, tiles, tile0, ntiles, s);
-    case 10: return launch_bulk_v<Q, ST, 256, 2, 3>(b, tiles, tile0, ntiles, s);
-    case 11: return launch_bulk_v<Q, ST, 512, 1, 5>(b, tiles, tile0, ntiles, s);
-    case 12: return launch_bulk_v<Q, ST, 256, 2, 5>(b, tiles, tile0, ntiles, s);
-    case 13: return launch_bulk_v<Q, ST, 256, 2, 5>(b, tiles, tile0, ntiles, s);
-    case 14: return launch_bulk_v<Q, ST, 256, 1, 4>(b, tiles, tile0, ntiles, s);
-    case 15: return launch_bulk_v<Q, ST, 512, 1, 12>(b, tiles, tile0, ntiles, s);
-    case 16: return launch_bulk_v<Q, ST, 512, 1, 13>(b, tiles, tile0, ntiles, s);
-    case 17: return launch_bulk_v<Q, ST, 256, 2, 13>(b, tiles, tile0, ntiles, s);
-    case 18: return launch_bulk_v<Q, ST, 256, 2, 13>(b, tiles, tile0, ntiles, s);
-    default: return launch_bulk_v<Q, ST, 256, 1, 0>(b, tiles, tile0, ntiles, s);
+    case 1: return launch_bulk_v<Q, ST, 256, 1, 0>(b, tiles, tile0, ntiles, faces, s);
+    case 2: return launch_bulk_v<Q, ST, 128, 1, 0>(b, tiles, tile0, ntiles, faces, s);
+    case 3: return launch_bulk_v<Q, ST, 512, 1, 0>(b, tiles, tile0, ntiles, faces, s);
+    case 4: return launch_bulk_v<Q, ST, 256, 2, 0>(b, tiles, tile0, ntiles, faces, s);
+    case 5: return launch_bulk_v<Q, ST, 256, 2, 0>(b, tiles, tile0, ntiles, faces, s);
+    case 6: return launch_bulk_v<Q, ST, 512, 1, 1>(b, tiles, tile0, ntiles, faces, s);
+    case 7: return launch_bulk_v<Q, ST, 256, 2, 1>(b, tiles, tile0, ntiles, faces, s);
+    case 8: return launch_bulk_v<Q, ST, 256, 2, 1>(b, tiles, tile0, ntiles, faces, s);
+    case 9: return launch_bulk_v<Q, ST, 512, 1, 3>(b, tiles, tile0, ntiles, faces, s);
+    case 10: return launch_bulk_v<Q, ST, 256, 2, 3>(b, tiles, tile0, ntiles, faces, s);
+    case 11: return launch_bulk_v<Q, ST, 512, 1, 5>(b, tiles, tile0, ntiles, faces, s);
+    case 12: return launch_bulk_v<Q, ST, 256, 2, 5>(b, tiles, tile0, ntiles, faces, s);
+    case 13: return launch_bulk_v<Q, ST, 256, 2, 5>(b, tiles, tile0, ntiles, faces, s);
+    case 14: return launch_bulk_v<Q, ST, 256, 1, 4>(b, tiles, tile0, ntiles, faces, s);
+    case 15: return launch_bulk_v<Q, ST, 512, 1, 12>(b, tiles, tile0, ntiles, faces, s);
+    case 16: return launch_bulk_v<Q, ST, 512, 1, 13>(b, tiles, tile0, ntiles, faces, s);
+    case 17: return launch_bulk_v<Q, ST, 256, 2, 13>(b, tiles, tile0, ntiles, faces, s);
+    case 18: return launch_bulk_v<Q, ST, 256, 2, 13>(b, tiles, tile0, ntiles, faces, s);
+    default: return launch_bulk_v<Q, ST, 256, 1, 0>(b, tiles, tile0, ntiles, faces, s);
   }
 }
 
 template <int Q, int ST>
 static hipError_t launch_boundary(const StepBuffers& b, const Region* regions,
                                   const BoxTile* btiles, int bt0, int nbt, uint2* list,
-                                  uint32_t cap, uint32_t* count, int nwg, int nfb, int stat0,
+                                  uint32_t cap, uint32_t* count, int nwg, int nwall, int stat0,
                                   hipStream_t s) {
-  if (nbt <= 0 || nwg <= 0 || nfb <= 0) return hipSuccess;
+  if (nbt <= 0 || (nwg <= 0 && nwall <= 0)) return hipSuccess;
   hipLaunchKernelGGL((k_boundary_scan<Q>), dim3(nbt), dim3(256), 0, s, b.insts, regions, btiles,
                      bt0, b.flags, list, cap, count);
-  hipLaunchKernelGGL((k_boundary_face<Q, ST>), dim3(nfb), dim3(64), 0, s, b, list + cap,
-                     count + 1, cap, stat0 + nwg);
-  hipLaunchKernelGGL((k_boundary_wave<Q, ST>), dim3(nwg), dim3(64), 0, s, b, list, count, cap,
-                     stat0);
+  if (nwg > 0)
+    hipLaunchKernelGGL((k_boundary_wave<Q, ST>), dim3(nwg), dim3(64), 0, s, b, list, count, cap,
+                       stat0);
+  if (nwall > 0)
+    hipLaunchKernelGGL((k_boundary_wall<Q, ST>), dim3(nwall), dim3(64), 0, s, b, list + cap,
+                       count + 1, cap, stat0 + nwg);
   return hipGetLastError();
 }
 
@@ -1627,6 +1775,7 @@ static hipError_t launch_geometry(int stage, const InstDev* insts, const Region*
                                   const BoxTile* gtiles, int ngt, void* src, uint8_t* flags,
                                   const int64_t* clock, int toff, hipStream_t s) {
   if (ngt <= 0) return hipSuccess;
+  if (stage == 1) return hipSuccess;   // the fresh-node refill runs in stage 0
   hipLaunchKernelGGL((k_geometry<Q, ST>), dim3(ngt), dim3(256), 0, s, stage, insts, regions,
                      gtiles, src, flags, clock, toff);
   return hipGetLastError();
@@ -1647,6 +1796,15 @@ static hipError_t launch_decode(const InstDev* insts, int inst, int64_t N, const
                                 double* f, hipStream_t s) {
   hipLaunchKernelGGL((k_decode<Q, ST>), dim3(grid_for(N, 256)), dim3(256), 0, s, insts, inst, N,
                      buf, f);
+  return hipGetLastError();
+}
+
+template <int Q, int ST>
+static hipError_t launch_decode_box(const InstDev* insts, int inst, const int* lo, const int* ext,
+                                    const void* buf, double* f, hipStream_t s) {
+  const int64_t Nb = (int64_t)ext[0] * ext[1] * ext[2];
+  hipLaunchKernelGGL((k_decode_box<Q, ST>), dim3(grid_for(Nb, 256)), dim3(256), 0, s, insts, inst,
+                     make_int3(lo[0], lo[1], lo[2]), make_int3(ext[0], ext[1], ext[2]), buf, f);
   return hipGetLastError();
 }
 
@@ -1694,7 +1852,8 @@ template <int Q, int ST>
 static const Ops* ops_for() {
   static const Ops o = {launch_bulk<Q, ST>,    launch_boundary<Q, ST>, launch_geometry<Q, ST>,
                         launch_init<Q, ST>,    launch_decode<Q, ST>,   launch_encode<Q, ST>,
-                        launch_moments<Q, ST>, launch_fixup<Q, ST>,    launch_force<Q, ST>};
+                        launch_moments<Q, ST>, launch_fixup<Q, ST>,    launch_force<Q, ST>,
+                        launch_decode_box<Q, ST>};
   return &o;
 }
 

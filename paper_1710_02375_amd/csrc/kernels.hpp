@@ -41,23 +41,30 @@ struct StepBuffers {
 
 struct Ops {
   // Bulk stream-collide over tiles [tile0, tile0 + ntiles) for nodes with no
-  // special flag.  Statistics go to stats[tile index].
+  // special flag, and the inflow / outflow plane nodes of those tiles.
+  // Statistics go to stats[tile index].
+  // faces: some instance of the launch has an inflow or outflow face; the
+  // kernel then also forms the equilibria of those plane nodes (after its
+  // main loop), otherwise the instantiation without that loop runs.
   hipError_t (*bulk)(int variant, const StepBuffers& b, const Tile* tiles, int tile0, int ntiles,
-                     hipStream_t s);
-  // Special nodes (faces, cut links) of the scanned box tiles [bt0, bt0+nbt):
-  // a scan appends the nodes with missing populations to list[0, cap) through
-  // count[0] and the inflow / outflow plane nodes to list[cap, 2 cap) through
-  // count[1]; then nwg one-wavefront workgroups stream the first with Grad's
-  // approximation and collide them, and nfb workgroups of 64 threads write
-  // the face equilibria (their collision is the identity).  Both counts must
-  // be zero on entry (the
-  // FP64 pass clears them).  Statistics go to stats[stat0, stat0 + nwg + nfb).
+                     bool faces, hipStream_t s);
+  // Nodes with missing populations of the scanned box tiles [bt0, bt0+nbt):
+  // a scan appends the nodes with a cut link to a body to list[0, cap)
+  // through count[0] and the nodes whose missing populations all come from
+  // wall faces to list[cap, 2 cap) through count[1]; then nwg one-wavefront
+  // workgroups fill and collide the first (one node per wavefront in 3D, two
+  // in 2D) and nwall workgroups of 64 threads the second (one node per
+  // thread).  Inflow and outflow plane nodes are handled by the bulk kernel.
+  // Either workgroup count may be zero (no body, no wall face): that kernel
+  // is not launched.  Both counts must be zero on entry (the FP64 pass
+  // clears them).  Statistics go to stats[stat0, stat0 + nwg + nwall).
   hipError_t (*boundary)(const StepBuffers& b, const Region* regions, const BoxTile* btiles,
                          int bt0, int nbt, uint2* list, uint32_t cap, uint32_t* count, int nwg,
-                         int nfb, int stat0, hipStream_t s);
-  // Geometry update over the swept boxes at time clock + toff:
-  // stage 0 marks SOLID_NEXT, stage 1 refills fresh nodes of src, stage 2
-  // makes SOLID_NEXT current and marks the cut-link (BODY) nodes.
+                         int nwall, int stat0, hipStream_t s);
+  // Geometry update over the swept boxes at time clock + toff: stage 0 marks
+  // SOLID_NEXT and refills the fresh nodes of src, stage 1 does nothing (kept
+  // for the call sequence), stage 2 makes SOLID_NEXT current and marks the
+  // cut-link (BODY) nodes.
   hipError_t (*geometry)(int stage, const InstDev* insts, const Region* regions,
                          const BoxTile* gtiles, int ngt, void* src, uint8_t* flags,
                          const int64_t* clock, int toff, hipStream_t s);
@@ -85,6 +92,9 @@ struct Ops {
                       const int64_t* clock, const double* xq, const double* nq,
                       const double* wq, int nqp, double* traction, double* partials,
                       int* nparts, hipStream_t s);
+  // Full populations of the box [lo, lo + ext) (x-fastest, population-major).
+  hipError_t (*decode_box)(const InstDev* insts, int inst, const int* lo, const int* ext,
+                           const void* buf, double* f, hipStream_t s);
 };
 
 const Ops* get_ops(int Q, int storage);

@@ -98,6 +98,8 @@ def lib():
                                              C.POINTER(C.c_double)]
         L.lbm_get_populations.argtypes = [vp, C.c_int, _dp]
         L.lbm_set_populations.argtypes = [vp, C.c_int, _dp]
+        L.lbm_get_populations_box.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                              _dp]
         L.lbm_set_stats.argtypes = [vp, C.c_int]
         L.lbm_set_launch_mode.argtypes = [vp, C.c_int]
         L.lbm_autotune.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int)]
@@ -117,7 +119,8 @@ def lib():
 
 
 EXPORTED = ["lbm_create", "lbm_destroy", "lbm_init_fields", "lbm_set_geometry", "lbm_step",
-            "lbm_moments", "lbm_wall_force", "lbm_wall_force_noalloc", "lbm_get_populations", "lbm_set_populations",
+            "lbm_moments", "lbm_wall_force", "lbm_wall_force_noalloc", "lbm_get_populations",
+            "lbm_set_populations", "lbm_get_populations_box",
             "lbm_set_stats", "lbm_set_launch_mode", "lbm_autotune", "lbm_set_variant",
             "lbm_variant_count", "lbm_variant_name", "lbm_info", "lbm_synchronize",
             "lbm_status_string", "lbm_last_error"]
@@ -296,6 +299,17 @@ def lbm_get_populations(ctx, inst, Q, N):
     f = np.zeros(Q * N)
     _check(ctx, lib().lbm_get_populations(ctx, int(inst), f))
     return f.reshape(Q, N)
+
+
+def lbm_get_populations_box(ctx, inst, Q, lo, hi):
+    """Populations of the box [lo, hi) (3 ints each; periodic axes may wrap
+    once) as an array (Q, nz_b, ny_b, nx_b)."""
+    lo3 = (C.c_int * 3)(*[int(v) for v in lo])
+    hi3 = (C.c_int * 3)(*[int(v) for v in hi])
+    ext = [int(h) - int(l) for l, h in zip(lo, hi)]
+    f = np.zeros(Q * ext[0] * ext[1] * ext[2])
+    _check(ctx, lib().lbm_get_populations_box(ctx, int(inst), lo3, hi3, f))
+    return f.reshape(Q, ext[2], ext[1], ext[0])
 
 
 def lbm_set_populations(ctx, inst, f):
