@@ -77,6 +77,8 @@ def lib():
         L.orc_stream_only.argtypes = [C.c_void_p]
         L.orc_grad_targets.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _dp]
         L.orc_set_time.argtypes = [C.c_void_p, C.c_long]
+        L.orc_set_mesh.argtypes = [C.c_void_p, C.c_int, _dp, _dp, C.c_int, _ip]
+        L.orc_body_velocity.argtypes = [C.c_void_p, _dp, C.c_double, _dp]
         _lib = L
     return _lib
 
@@ -273,6 +275,26 @@ class Domain:
         if k <= 0:
             return None
         return dict(rho=out[0], u=out[1:4].copy(), grad=out[4:13].reshape(3, 3).copy(), missing=k)
+
+    def set_mesh(self, verts, vel, tris):
+        """Surface-mesh body (Sec. II.C.1): verts (V, 3), vel (V, 3), tris
+        (T, 3) vertex indices (2D: the first two of each row form a segment);
+        sets the geometry at the current time."""
+        V = _f64(np.asarray(verts).reshape(-1, 3))
+        Vv = _f64(np.asarray(vel).reshape(-1, 3))
+        T = np.ascontiguousarray(np.asarray(tris).reshape(-1, 3), dtype=np.int32)
+        if lib().orc_set_mesh(self._h, V.shape[0], V.ravel(), Vv.ravel(), T.shape[0],
+                              T.ravel()) != 0:
+            raise ValueError("oracle: invalid mesh")
+
+    def body_velocity(self, x, t=None):
+        """Velocity of the body at point x (mesh: interpolated at the closest
+        surface point)."""
+        xx = np.zeros(3)
+        xx[: len(x)] = x
+        v = np.zeros(3)
+        lib().orc_body_velocity(self._h, xx, float(self.time if t is None else t), v)
+        return v
 
     def set_time(self, t):
         """Sets the step count of the stored state (then call set_body)."""

@@ -316,10 +316,161 @@ double round_storage(int mode, double x) {
 //          or y > y_hi; each plate moves tangentially with its own velocity.
 // Points on the surface count as solid.
 // ---------------------------------------------------------------------------
+//   kind 3 mesh: a closed surface mesh (Sec. II.C.1: the structure's surface
+//          split into triangles, vertices at their computed positions, vertex
+//          velocities interpolated at the link intersections); in 2D each
+//          face is the segment of its first two vertices.  Solid: inside or on
+//          the surface, by the generalized winding number (sum of the solid
+//          angles the triangles subtend, over 4 pi; in 2D the sum of the
+//          angles the segments subtend, over 2 pi), larger than 1/2 in
+//          magnitude (either orientation of the faces).  The
+//          velocity at a point is the vertex velocities interpolated linearly
+//          at the closest point of the surface.  The mesh holds at every time.
 struct Body {
   int kind = 0;
   double p[16] = {};
+  std::vector<double> mv, mvel;   // mesh vertices and their velocities (3 each)
+  std::vector<int> mt;            // mesh faces (3 vertex indices each)
 };
+
+// Generalized winding number of a closed triangle mesh at x: the sum over the
+// triangles of the signed solid angle they subtend at x (the formula of van
+// Oosterom and Strackee, tan(Omega/2) = a.(b x c) / (|a||b||c| + (a.b)|c|
+// + (b.c)|a| + (c.a)|b|) with a, b, c the vertices relative to x), over 4 pi.
+double winding_3d(const Body& b, const double* x) {
+  double sum = 0.0;
+  const size_t nt = b.mt.size() / 3;
+  for (size_t k = 0; k < nt; ++k) {
+    double v[3][3];
+    for (int j = 0; j < 3; ++j)
+      for (int a = 0; a < 3; ++a) v[j][a] = b.mv[3 * b.mt[3 * k + j] + a] - x[a];
+    const double la = std::sqrt(v[0][0] * v[0][0] + v[0][1] * v[0][1] + v[0][2] * v[0][2]);
+    const double lb = std::sqrt(v[1][0] * v[1][0] + v[1][1] * v[1][1] + v[1][2] * v[1][2]);
+    const double lc = std::sqrt(v[2][0] * v[2][0] + v[2][1] * v[2][1] + v[2][2] * v[2][2]);
+    const double det = v[0][0] * (v[1][1] * v[2][2] - v[1][2] * v[2][1]) -
+                       v[0][1] * (v[1][0] * v[2][2] - v[1][2] * v[2][0]) +
+                       v[0][2] * (v[1][0] * v[2][1] - v[1][1] * v[2][0]);
+    auto dot = [&](int i, int j) {
+      return v[i][0] * v[j][0] + v[i][1] * v[j][1] + v[i][2] * v[j][2];
+    };
+    const double den = la * lb * lc + dot(0, 1) * lc + dot(1, 2) * la + dot(2, 0) * lb;
+    sum += 2.0 * std::atan2(det, den);
+  }
+  return sum / (4.0 * M_PI);
+}
+
+// Winding number of a closed polygon (segments of the first two vertices of
+// each face) at x in the plane: the sum of the signed angles the segments
+// subtend, over 2 pi.
+double winding_2d(const Body& b, const double* x) {
+  double sum = 0.0;
+  const size_t nt = b.mt.size() / 3;
+  for (size_t k = 0; k < nt; ++k) {
+    const double* p0 = &b.mv[3 * b.mt[3 * k]];
+    const double* p1 = &b.mv[3 * b.mt[3 * k + 1]];
+    const double ax = p0[0] - x[0], ay = p0[1] - x[1], bx = p1[0] - x[0], by = p1[1] - x[1];
+    sum += std::atan2(ax * by - ay * bx, ax * bx + ay * by);
+  }
+  return sum / (2.0 * M_PI);
+}
+
+// Closest point of triangle (a, b, c) to x, written from the region
+// classification of the plane of the triangle: the point's projection if its
+// barycentric coordinates are all positive, else the closest point of the
+// nearest edge.  Returns the squared distance and the barycentric
+// coordinates (l0, l1, l2) of the closest point.
+double closest_on_triangle(const double* a, const double* b, const double* c, const double* x,
+                           double* l) {
+  // Minimise |x - (a + s (b - a) + t (c - a))|^2 over the triangle: the
+  // unconstrained minimiser, then the three edges if it lies outside.
+  double e0[3], e1[3], d[3];
+  for (int k = 0; k < 3; ++k) {
+    e0[k] = b[k] - a[k];
+    e1[k] = c[k] - a[k];
+    d[k] = a[k] - x[k];
+  }
+  auto dt = [](const double* u, const double* v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; };
+  const double A = dt(e0, e0), B = dt(e0, e1), C = dt(e1, e1), Dv = dt(e0, d), E = dt(e1, d);
+  auto dist2 = [&](double s, double t) {
+    double r = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double v = d[k] + s * e0[k] + t * e1[k];
+      r += v * v;
+    }
+    return r;
+  };
+  const double det = A * C - B * B;
+  double best_s = 0.0, best_t = 0.0, best = 1e300;
+  if (det > 0.0) {
+    const double s = (B * E - C * Dv) / det, t = (B * Dv - A * E) / det;
+    if (s >= 0.0 && t >= 0.0 && s + t <= 1.0) {
+      best_s = s;
+      best_t = t;
+      best = dist2(s, t);
+    }
+  }
+  if (best == 1e300) {
+    // Edges: a-b (t = 0), a-c (s = 0), b-c (s + t = 1), each a clamped 1-D
+    // minimisation.
+    auto clamp01 = [](double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); };
+    {
+      const double s = A > 0.0 ? clamp01(-Dv / A) : 0.0;
+      const double r = dist2(s, 0.0);
+      if (r < best) { best = r; best_s = s; best_t = 0.0; }
+    }
+    {
+      const double t = C > 0.0 ? clamp01(-E / C) : 0.0;
+      const double r = dist2(0.0, t);
+      if (r < best) { best = r; best_s = 0.0; best_t = t; }
+    }
+    {
+      // s = 1 - t: minimise over t of |d + e0 + t (e1 - e0)|^2.
+      const double f = C - 2.0 * B + A;
+      const double t = f > 0.0 ? clamp01((A + Dv - B - E) / f) : 0.0;
+      const double r = dist2(1.0 - t, t);
+      if (r < best) { best = r; best_s = 1.0 - t; best_t = t; }
+    }
+  }
+  l[0] = 1.0 - best_s - best_t;
+  l[1] = best_s;
+  l[2] = best_t;
+  return best;
+}
+
+// Velocity at the closest point of the mesh to x (D = 2: segments).
+void mesh_velocity(const Body& b, int D, const double* x, double* v) {
+  double best = 1e300;
+  v[0] = v[1] = v[2] = 0.0;
+  const size_t nt = b.mt.size() / 3;
+  for (size_t k = 0; k < nt; ++k) {
+    double l[3];
+    double r;
+    const int i0 = b.mt[3 * k], i1 = b.mt[3 * k + 1], i2 = b.mt[3 * k + 2];
+    if (D == 3) {
+      r = closest_on_triangle(&b.mv[3 * i0], &b.mv[3 * i1], &b.mv[3 * i2], x, l);
+    } else {
+      // Segment p0-p1 in the plane: clamped projection.
+      const double* p0 = &b.mv[3 * i0];
+      const double* p1 = &b.mv[3 * i1];
+      const double ex = p1[0] - p0[0], ey = p1[1] - p0[1];
+      const double len2 = ex * ex + ey * ey;
+      double s = len2 > 0.0 ? ((x[0] - p0[0]) * ex + (x[1] - p0[1]) * ey) / len2 : 0.0;
+      s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
+      const double dx = p0[0] + s * ex - x[0], dy = p0[1] + s * ey - x[1];
+      r = dx * dx + dy * dy;
+      l[0] = 1.0 - s;
+      l[1] = s;
+      l[2] = 0.0;
+    }
+    if (r < best) {
+      best = r;
+      for (int a = 0; a < 3; ++a)
+        v[a] = l[0] * b.mvel[3 * i0 + a] + l[1] * b.mvel[3 * i1 + a] +
+               (D == 3 ? l[2] * b.mvel[3 * i2 + a] : 0.0);
+    }
+  }
+  if (D == 2) v[2] = 0.0;
+}
 
 bool body_inside(const Body& b, int D, const double* x, double t) {
   switch (b.kind) {
@@ -337,6 +488,8 @@ bool body_inside(const Body& b, int D, const double* x, double t) {
       const double xc = b.p[0] + b.p[3] * std::sin(b.p[4] * t + b.p[5]) * (s / b.p[1]) * (s / b.p[1]);
       return std::fabs(x[0] - xc) <= 0.5 * b.p[2];
     }
+    case 3:
+      return std::fabs(D == 3 ? winding_3d(b, x) : winding_2d(b, x)) > 0.5;
     case 4:
       return x[1] < b.p[0] || x[1] > b.p[1];
     default:
@@ -356,6 +509,9 @@ void body_velocity(const Body& b, int D, const double* x, double t, double* v) {
       v[0] = b.p[3] * b.p[4] * std::cos(b.p[4] * t + b.p[5]) * (s / b.p[1]) * (s / b.p[1]);
       break;
     }
+    case 3:
+      mesh_velocity(b, D, x, v);
+      break;
     case 4: {
       const double* u = (x[1] < 0.5 * (b.p[0] + b.p[1])) ? &b.p[2] : &b.p[5];
       for (int a = 0; a < D; ++a) v[a] = u[a];
@@ -984,7 +1140,7 @@ int orc_get_precollision(void* h, double* f) {
 // Sets the body and the geometry at the current time.
 int orc_set_body(void* h, int kind, const double* params) {
   Domain* d = static_cast<Domain*>(h);
-  if (kind < 0 || kind > 4 || kind == 3) return -1;
+  if (kind < 0 || kind > 4 || kind == 3) return -1;   // meshes: orc_set_mesh
   if (kind == 2 && d->L->D != 2) return -1;
   d->body.kind = kind;
   for (int k = 0; k < 16; ++k) d->body.p[k] = params ? params[k] : 0.0;
@@ -1031,6 +1187,14 @@ int orc_grad_targets(void* h, int x, int y, int z, double* out) {
   return cnt;
 }
 
+// Velocity of the body at point x at time t (for a mesh: the vertex
+// velocities interpolated at the closest surface point).
+int orc_body_velocity(void* h, const double* x, double t, double* v) {
+  const Domain* d = static_cast<const Domain*>(h);
+  body_velocity(d->body, d->L->D, x, t, v);
+  return 0;
+}
+
 // Sets the step count (the time of the stored state), e.g. before stepping
 // from a state read back from elsewhere; the geometry is not rebuilt (call
 // orc_set_body after this).
@@ -1038,6 +1202,33 @@ int orc_set_time(void* h, long t) {
   Domain* d = static_cast<Domain*>(h);
   if (t < 0) return -1;
   d->step = t;
+  return 0;
+}
+
+// Sets a surface-mesh body (kind 3): nv vertices (3 coordinates each), their
+// velocities, nt faces (3 vertex indices each; in 2D the first two).  The
+// mesh is the surface at the time of the next step's new state; if the body
+// was not a mesh before, it also sets the geometry at the current time (a mesh
+// replacing a mesh leaves the current geometry, so that the next step refills
+// the nodes it uncovers).  Returns -1 for an index out of range.
+int orc_set_mesh(void* h, int nv, const double* verts, const double* vel, int nt, const int* tris) {
+  Domain* d = static_cast<Domain*>(h);
+  if (nv < 1 || nt < 1) return -1;
+  for (int k = 0; k < 3 * nt; ++k)
+    if (tris[k] < 0 || tris[k] >= nv) return -1;
+  const bool was_mesh = d->body.kind == 3;
+  d->body.kind = 3;
+  d->body.mv.assign(verts, verts + 3 * nv);
+  d->body.mvel.assign(vel, vel + 3 * nv);
+  d->body.mt.assign(tris, tris + 3 * nt);
+  if (was_mesh) return 0;
+  const double t = (double)d->step;
+#pragma omp parallel for schedule(static) num_threads(d->nthreads)
+  for (long n = 0; n < d->N; ++n) {
+    int x[3];
+    coords(*d, n, x);
+    d->solid[n] = inside_at(*d, x, t) ? 1 : 0;
+  }
   return 0;
 }
 

@@ -16,7 +16,8 @@ import oracle
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-# (name, original text, planted text, pin, pin arguments)
+# (name, original text, planted text, pin ("module:function", or a function of
+# test_oracle_domain), pin arguments)
 CASES = [
     # Wall stress extrapolated from the far probe instead of to the wall.
     ("stress_extrapolation_reversed",
@@ -91,6 +92,30 @@ CASES = [
      "for (int a = 0; a < D; ++a) r2 += (q[a] - p[a]) * (q[a] - p[a]);",
      "for (int a = 0; a < D; ++a) r2 = std::max(r2, std::fabs(q[a] - p[a]));",
      "test_probe_fallback_nearest_fluid_node_brute_force", (9,)),
+    # Solid angle of a triangle without its factor 2 (winding number halved).
+    ("mesh_solid_angle_half",
+     "    sum += 2.0 * std::atan2(det, den);", "    sum += std::atan2(det, den);",
+     "test_oracle_mesh:test_cube_mesh_solid_is_the_box", (False,)),
+    # 2D winding with the cross and dot products exchanged.
+    ("mesh_polygon_angle_swapped",
+     "    sum += std::atan2(ax * by - ay * bx, ax * bx + ay * by);",
+     "    sum += std::atan2(ax * bx + ay * by, ax * by - ay * bx);",
+     "test_oracle_mesh:test_square_polygon_solid_is_the_square_2d", ()),
+    # Mesh velocity interpolated with the second and third vertices exchanged.
+    ("mesh_velocity_vertices_swapped",
+     "        v[a] = l[0] * b.mvel[3 * i0 + a] + l[1] * b.mvel[3 * i1 + a] +",
+     "        v[a] = l[0] * b.mvel[3 * i0 + a] + l[1] * b.mvel[3 * i2 + a] +",
+     "test_oracle_mesh:test_rigid_motion_targets_exact_on_mesh", (27,)),
+    # Closest point on the third edge with a sign error.
+    ("mesh_closest_edge_sign",
+     "      const double t = f > 0.0 ? clamp01((A + Dv - B - E) / f) : 0.0;",
+     "      const double t = f > 0.0 ? clamp01((A - Dv - B - E) / f) : 0.0;",
+     "test_oracle_mesh:test_mesh_velocity_at_closest_point_of_a_box", ()),
+    # Closest point on the first edge unclamped.
+    ("mesh_closest_edge_unclamped",
+     "      const double s = A > 0.0 ? clamp01(-Dv / A) : 0.0;",
+     "      const double s = A > 0.0 ? -Dv / A : 0.0;",
+     "test_oracle_mesh:test_mesh_velocity_at_closest_point_of_a_box", ()),
 ]
 
 CHILD = textwrap.dedent("""
@@ -100,9 +125,11 @@ CHILD = textwrap.dedent("""
     oracle._SRC = {src!r}
     oracle._LIB = {lib!r}
     oracle.build(force=True)
-    import test_oracle_domain as T
+    import importlib
+    mod, _, fn = {pin!r}.rpartition(":")
+    T = importlib.import_module(mod or "test_oracle_domain")
     try:
-        getattr(T, {pin!r})(oracle, *{args!r})
+        getattr(T, fn)(oracle, *{args!r})
     except AssertionError:
         print("PIN FAILED")
         sys.exit(0)

@@ -236,3 +236,37 @@ def plate_quadrature(y, normal_sign, nx, width=1.0):
     n = np.zeros((nx, 2))
     n[:, 1] = normal_sign
     return xq, n, np.full(nx, width)
+
+
+# ---------------------------------------------------------------------------
+# Surface meshes (closed; positions and faces only)
+# ---------------------------------------------------------------------------
+
+
+def cube_mesh(lo, hi):
+    """Axis-aligned box [lo, hi] as 8 vertices and 12 outward-oriented
+    triangles."""
+    lo, hi = np.asarray(lo, dtype=np.float64), np.asarray(hi, dtype=np.float64)
+    V = np.array([[(hi if (k >> a) & 1 else lo)[a] for a in range(3)] for k in range(8)])
+    quads = [(0, 2, 3, 1), (4, 5, 7, 6), (0, 1, 5, 4), (2, 6, 7, 3), (0, 4, 6, 2), (1, 3, 7, 5)]
+    T = []
+    for a, b, c, d in quads:
+        T += [(a, b, c), (a, c, d)]
+    return V, np.array(T, dtype=np.int64)
+
+
+def sphere_mesh(center, radius, subdiv=3):
+    """Icosphere with its vertices on the sphere (radius, center)."""
+    V, T = icosphere(subdiv)
+    return V * radius + np.asarray(center, dtype=np.float64), T
+
+
+def circle_polygon(center, radius, count=64):
+    """Closed polygon with its vertices on a circle, as 2D 'faces' (segments
+    of the first two indices; z = 0)."""
+    th = 2.0 * math.pi * np.arange(count) / count
+    V = np.zeros((count, 3))
+    V[:, 0] = center[0] + radius * np.cos(th)
+    V[:, 1] = center[1] + radius * np.sin(th)
+    T = np.stack([np.arange(count), (np.arange(count) + 1) % count, np.arange(count)], 1)
+    return V, T.astype(np.int64)
