@@ -55,6 +55,16 @@ struct lbm_ctx {
   std::vector<char> has_faces;    // an inflow or outflow face
   bool any_faces = false;
   std::vector<char> force_valid;
+  // Device arrays of surface-mesh bodies, per instance (grown on demand).
+  struct MeshBuf {
+    double* v = nullptr;   size_t v_cap = 0;    // positions then velocities
+    int* f = nullptr;      size_t f_cap = 0;    // faces
+    int* cs = nullptr;     size_t cs_cap = 0;   // column starts
+    double* cx = nullptr;  size_t cx_cap = 0;   // column crossings
+    int* bs = nullptr;     size_t bs_cap = 0;   // cell starts
+    int* bf = nullptr;     size_t bf_cap = 0;   // cell faces
+  };
+  std::vector<MeshBuf> mesh;
   double* force_ws = nullptr;     // wall-force workspace, grown on demand
   size_t force_ws_doubles = 0;
   double* scratch = nullptr;      // device address of `scratch` on this device
@@ -555,6 +565,175 @@ lbm_status full_geometry(lbm_ctx* c, int k) {
   return st;
 }
 
+// ---------------------------------------------------------------------------
+// Surface-mesh bodies: host-side indexes built at lbm_set_geometry (O(faces)
+// work; the surface comes from the structure solver on the host).
+// ---------------------------------------------------------------------------
+struct MeshHost {
+  std::vector<double> v;    // positions (3 per vertex) then velocities
+  std::vector<int> f;       // faces (3 per face)
+  std::vector<int> cs;      // column starts (ncols + 1)
+  std::vector<double> cx;   // crossings, ascending per column
+  std::vector<int> bs;      // cell starts (ncells + 1)
+  std::vector<int> bf;      // faces per cell
+  int col_lo[2], col_n[2];
+  double bin_lo[3], bin_h;
+  int bin_n[3];
+};
+
+// Crossings of the lattice lines along x (columns (y, z) of the box) with
+// the surface.  3D: a column point inside a face's (y, z) projection, with a
+// tie rule that gives a point on an edge shared by two faces to exactly one
+// of them (edge functions evaluated in one canonical direction per edge);
+// the crossing is the face's plane at that point.  2D: the even-odd rule with
+// half-open y intervals per segment.
+void mesh_columns(int D, const int box_lo[3], const int box_hi[3], MeshHost& m) {
+  m.col_lo[0] = box_lo[1];
+  m.col_n[0] = std::max(box_hi[1] - box_lo[1], 0);
+  m.col_lo[1] = D == 3 ? box_lo[2] : 0;
+  m.col_n[1] = D == 3 ? std::max(box_hi[2] - box_lo[2], 0) : 1;
+  const size_t ncol = (size_t)m.col_n[0] * m.col_n[1];
+  std::vector<std::vector<double>> col(ncol);
+  const size_t nf = m.f.size() / 3;
+  const double* V = m.v.data();
+  auto push = [&](int y, int z, double x) {
+    const int a = y - m.col_lo[0], b = z - m.col_lo[1];
+    if (a < 0 || b < 0 || a >= m.col_n[0] || b >= m.col_n[1]) return;
+    col[(size_t)a + (size_t)m.col_n[0] * b].push_back(x);
+  };
+  for (size_t k = 0; k < nf; ++k) {
+    const int* fv = &m.f[3 * k];
+    if (D == 2) {
+      const double* p0 = V + 3 * fv[0];
+      const double* p1 = V + 3 * fv[1];
+      if (p0[1] == p1[1]) continue;
+      const double ylo = std::min(p0[1], p1[1]), yhi = std::max(p0[1], p1[1]);
+      for (int y = (int)std::ceil(ylo); (double)y < yhi; ++y)
+        push(y, 0, p0[0] + ((double)y - p0[1]) * (p1[0] - p0[0]) / (p1[1] - p0[1]));
+      continue;
+    }
+    // Projected vertices (u, w) = (y, z) and their x.
+    double P[3][2], X[3];
+    for (int j = 0; j < 3; ++j) {
+      P[j][0] = V[3 * fv[j] + 1];
+      P[j][1] = V[3 * fv[j] + 2];
+      X[j] = V[3 * fv[j]];
+    }
+    auto edge = [&](const double* a, const double* b, double u, double w) {
+      // cross(b - a, pt - a) evaluated from the lexicographically smaller end.
+      const bool fwd = a[0] < b[0] || (a[0] == b[0] && a[1] < b[1]);
+      const double* s0 = fwd ? a : b;
+      const double* s1 = fwd ? b : a;
+      const double e = (s1[0] - s0[0]) * (w - s0[1]) - (s1[1] - s0[1]) * (u - s0[0]);
+      return fwd ? e : -e;
+    };
+    double area = edge(P[0], P[1], P[2][0], P[2][1]);
+    if (area == 0.0) continue;
+    int o[3] = {0, 1, 2};
+    if (area < 0.0) std::swap(o[1], o[2]);   // counter-clockwise in (y, z)
+    auto included = [&](const double* a, const double* b) {
+      // Of an edge and its reverse exactly one is included.
+      const double dw = b[1] - a[1], du = b[0] - a[0];
+      return dw > 0.0 || (dw == 0.0 && du < 0.0);
+    };
+    const double umin = std::min({P[0][0], P[1][0], P[2][0]}), umax = std::max({P[0][0], P[1][0], P[2][0]});
+    const double wmin = std::min({P[0][1], P[1][1], P[2][1]}), wmax = std::max({P[0][1], P[1][1], P[2][1]});
+    for (int w = (int)std::ceil(wmin); (double)w <= wmax; ++w)
+      for (int u = (int)std::ceil(umin); (double)u <= umax; ++u) {
+        double E[3];
+        bool in = true;
+        for (int e = 0; e < 3 && in; ++e) {
+          const double* a = P[o[e]];
+          const double* b = P[o[(e + 1) % 3]];
+          E[e] = edge(a, b, (double)u, (double)w);
+          in = E[e] > 0.0 || (E[e] == 0.0 && included(a, b));
+        }
+        if (!in) continue;
+        const double sum = E[0] + E[1] + E[2];
+        if (!(sum > 0.0)) continue;
+        // E[e] is the edge o[e] -> o[e+1]: weight of the opposite vertex.
+        const double x = (E[1] * X[o[0]] + E[2] * X[o[1]] + E[0] * X[o[2]]) / sum;
+        push(u, w, x);
+      }
+  }
+  m.cs.assign(ncol + 1, 0);
+  m.cx.clear();
+  for (size_t k = 0; k < ncol; ++k) {
+    std::sort(col[k].begin(), col[k].end());
+    m.cs[k] = (int)m.cx.size();
+    m.cx.insert(m.cx.end(), col[k].begin(), col[k].end());
+  }
+  m.cs[ncol] = (int)m.cx.size();
+}
+
+// Faces by cell of a uniform grid of spacing 2 over the surface's bounding
+// box (one cell layer in z for 2D): each face listed in every cell its
+// bounding box meets.
+void mesh_cells(int D, MeshHost& m) {
+  const size_t nv = m.v.size() / 6, nf = m.f.size() / 3;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (size_t i = 0; i < nv; ++i)
+    for (int a = 0; a < D; ++a) {
+      lo[a] = std::min(lo[a], m.v[3 * i + a]);
+      hi[a] = std::max(hi[a], m.v[3 * i + a]);
+    }
+  m.bin_h = 2.0;
+  for (int a = 0; a < 3; ++a) {
+    if (a >= D) {
+      m.bin_lo[a] = -1.0;
+      m.bin_n[a] = 1;
+      continue;
+    }
+    m.bin_lo[a] = std::floor(lo[a]) - 2.0;
+    m.bin_n[a] = std::max(1, (int)std::ceil((hi[a] + 2.0 - m.bin_lo[a]) / m.bin_h));
+  }
+  const size_t ncell = (size_t)m.bin_n[0] * m.bin_n[1] * m.bin_n[2];
+  std::vector<std::vector<int>> cell(ncell);
+  const int nc = D == 3 ? 3 : 2;
+  for (size_t k = 0; k < nf; ++k) {
+    int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) {
+      double flo = 1e300, fhi = -1e300;
+      for (int j = 0; j < nc; ++j) {
+        flo = std::min(flo, m.v[3 * m.f[3 * k + j] + a]);
+        fhi = std::max(fhi, m.v[3 * m.f[3 * k + j] + a]);
+      }
+      c0[a] = std::max(0, (int)std::floor((flo - m.bin_lo[a]) / m.bin_h));
+      c1[a] = std::min(m.bin_n[a] - 1, (int)std::floor((fhi - m.bin_lo[a]) / m.bin_h));
+    }
+    for (int z = c0[2]; z <= c1[2]; ++z)
+      for (int y = c0[1]; y <= c1[1]; ++y)
+        for (int x = c0[0]; x <= c1[0]; ++x)
+          cell[(size_t)x + (size_t)m.bin_n[0] * ((size_t)y + (size_t)m.bin_n[1] * z)].push_back((int)k);
+  }
+  m.bs.assign(ncell + 1, 0);
+  m.bf.clear();
+  for (size_t k = 0; k < ncell; ++k) {
+    m.bs[k] = (int)m.bf.size();
+    m.bf.insert(m.bf.end(), cell[k].begin(), cell[k].end());
+  }
+  m.bs[ncell] = (int)m.bf.size();
+}
+
+template <typename T>
+lbm_status ensure_dev(lbm_ctx* c, T** p, size_t* cap, size_t need) {
+  if (need <= *cap && *p) return LBM_OK;
+  dev_free(c, *p);
+  *p = nullptr;
+  *cap = 0;
+  const size_t n = std::max<size_t>(need + need / 2, 16);
+  lbm_status st = dev_alloc(c, n * sizeof(T), (void**)p);
+  if (st) return st;
+  *cap = n;
+  return LBM_OK;
+}
+
+template <typename T>
+hipError_t put(lbm_ctx* c, T* dst, const std::vector<T>& v) {
+  if (v.empty()) return hipSuccess;
+  return hipMemcpyAsync(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream);
+}
+
 std::string cache_key(const lbm_ctx* c) {
   hipDeviceProp_t prop;
   std::string dev = "unknown";
@@ -637,6 +816,14 @@ lbm_status lbm_destroy(lbm_ctx* c) {
   dev_free(c, c->dgtiles);
   dev_free(c, c->dstats);
   dev_free(c, c->force_ws);
+  for (auto& m : c->mesh) {
+    dev_free(c, m.v);
+    dev_free(c, m.f);
+    dev_free(c, m.cs);
+    dev_free(c, m.cx);
+    dev_free(c, m.bs);
+    dev_free(c, m.bf);
+  }
   if (c->herr) (void)hipHostFree(c->herr);
   if (c->err_event) (void)hipEventDestroy(c->err_event);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -720,6 +907,7 @@ lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_
   c->moving.assign(n_instances, 0);
   c->has_body.assign(n_instances, 0);
   c->has_faces.assign(n_instances, 0);
+  c->mesh.assign(n_instances, lbm_ctx::MeshBuf());
   for (int k = 0; k < n_instances; ++k) {
     c->has_faces[k] = desc[k].face[0] == LBM_FACE_INLET || desc[k].face[1] == LBM_FACE_OUTLET;
     if (c->has_faces[k]) c->any_faces = true;
@@ -856,6 +1044,140 @@ lbm_status lbm_init_fields(lbm_ctx* c, int inst, const double* rho, const double
   return LBM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Surface-mesh body of instance inst: validates and copies the mesh, builds
+// its column crossings and face cells on the host, uploads them, and points
+// the instance descriptor at them.  A mesh replacing a mesh is the surface
+// at the next step's time: the current geometry is kept and the next step
+// refills what it uncovers; the swept box only grows (it covers the old
+// and the new surface), and while it does not change, the descriptor is
+// updated in place, so that captured graphs stay valid.
+lbm_status set_mesh(lbm_ctx* c, int inst, const lbm_body& b) {
+  const int D = c->D;
+  if (b.nverts < (D == 3 ? 3 : 2) || b.ntris < 1 || !b.verts || !b.vert_vel || !b.tris)
+    return fail(c, LBM_ERR_INVALID, "a mesh needs vertices, vertex velocities and faces");
+  MeshHost m;
+  m.v.assign(6 * (size_t)b.nverts, 0.0);
+  for (int i = 0; i < b.nverts; ++i)
+    for (int a = 0; a < 3; ++a) {
+      const double x = a < D ? b.verts[3 * i + a] : 0.0;
+      const double v = a < D ? b.vert_vel[3 * i + a] : 0.0;
+      if (!std::isfinite(x) || !std::isfinite(v) || !(std::fabs(v) < 1.0))
+        return fail(c, LBM_ERR_INVALID, "mesh vertex %d: non-finite coordinate or |velocity| >= 1", i);
+      m.v[3 * (size_t)i + a] = x;
+      m.v[3 * (size_t)b.nverts + 3 * (size_t)i + a] = v;
+    }
+  m.f.assign(b.tris, b.tris + 3 * (size_t)b.ntris);
+  for (size_t k = 0; k < m.f.size(); ++k) {
+    if (D == 2 && k % 3 == 2) m.f[k] = m.f[k - 2];   // unused in 2D
+    if (m.f[k] < 0 || m.f[k] >= b.nverts)
+      return fail(c, LBM_ERR_INVALID, "mesh face %zu: vertex index out of range", k / 3);
+  }
+  // Swept box: the surface's bounding box with a 2-node margin (as for the
+  // analytic bodies), joined with the previous box when a mesh replaces a
+  // mesh.
+  const lbm_instance_desc& d = c->desc[inst];
+  const int n[3] = {d.nx, d.ny, d.nz};
+  InstDev& I = c->hinst[inst];
+  const bool was_mesh = I.body_kind == LBM_BODY_MESH;
+  int lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a >= D) {
+      lo[a] = 0;
+      hi[a] = 1;
+      continue;
+    }
+    double mn = 1e300, mx = -1e300;
+    for (int i = 0; i < b.nverts; ++i) {
+      mn = std::min(mn, m.v[3 * (size_t)i + a]);
+      mx = std::max(mx, m.v[3 * (size_t)i + a]);
+    }
+    int l = (int)std::floor(mn) - 2, h = (int)std::ceil(mx) + 3;
+    if (was_mesh) {
+      l = std::min(l, I.box_lo[a]);
+      h = std::max(h, I.box_hi[a]);
+    }
+    if (l < 0 || h > n[a]) {
+      if (d.face[2 * a] == LBM_FACE_PERIODIC)
+        return fail(c, LBM_ERR_GEOMETRY, "the mesh's swept region crosses a periodic face");
+      l = std::max(l, 0);
+      h = std::min(h, n[a]);
+    }
+    if (h <= l) return fail(c, LBM_ERR_GEOMETRY, "the mesh lies outside the domain");
+    lo[a] = l;
+    hi[a] = h;
+  }
+  mesh_columns(D, lo, hi, m);
+  mesh_cells(D, m);
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  lbm_ctx::MeshBuf& mb = c->mesh[inst];
+  lbm_status st;
+  if ((st = ensure_dev(c, &mb.v, &mb.v_cap, m.v.size()))) return st;
+  if ((st = ensure_dev(c, &mb.f, &mb.f_cap, m.f.size()))) return st;
+  if ((st = ensure_dev(c, &mb.cs, &mb.cs_cap, m.cs.size()))) return st;
+  if ((st = ensure_dev(c, &mb.cx, &mb.cx_cap, std::max<size_t>(m.cx.size(), 1)))) return st;
+  if ((st = ensure_dev(c, &mb.bs, &mb.bs_cap, m.bs.size()))) return st;
+  if ((st = ensure_dev(c, &mb.bf, &mb.bf_cap, std::max<size_t>(m.bf.size(), 1)))) return st;
+  hipError_t e = put(c, mb.v, m.v);
+  if (e == hipSuccess) e = put(c, mb.f, m.f);
+  if (e == hipSuccess) e = put(c, mb.cs, m.cs);
+  if (e == hipSuccess) e = put(c, mb.cx, m.cx);
+  if (e == hipSuccess) e = put(c, mb.bs, m.bs);
+  if (e == hipSuccess) e = put(c, mb.bf, m.bf);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(c, LBM_ERR_DEVICE, "mesh upload: %s", hipGetErrorString(e));
+  if (I.flag_off < 0) {
+    int64_t foff = 0;
+    for (int k = 0; k < inst; ++k) foff += (c->hinst[k].N + 255) / 256 * 256;
+    I.flag_off = foff;
+  }
+  const bool same_box = was_mesh && std::equal(lo, lo + 3, I.box_lo) && std::equal(hi, hi + 3, I.box_hi);
+  I.body_kind = LBM_BODY_MESH;
+  for (int k = 0; k < 16; ++k) I.body[k] = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    I.box_lo[a] = lo[a];
+    I.box_hi[a] = hi[a];
+  }
+  I.mesh_v = mb.v;
+  I.mesh_vel = mb.v + 3 * (size_t)b.nverts;
+  I.mesh_f = mb.f;
+  I.mesh_nf = b.ntris;
+  I.col_start = mb.cs;
+  I.col_x = mb.cx;
+  I.bin_start = mb.bs;
+  I.bin_face = mb.bf;
+  for (int a = 0; a < 2; ++a) {
+    I.col_lo[a] = m.col_lo[a];
+    I.col_n[a] = m.col_n[a];
+  }
+  for (int a = 0; a < 3; ++a) {
+    I.bin_lo[a] = m.bin_lo[a];
+    I.bin_n[a] = m.bin_n[a];
+  }
+  I.bin_h = m.bin_h;
+  c->has_body[inst] = 1;
+  c->moving[inst] = 1;   // the geometry stages read the mesh every step
+  c->force_valid[inst] = 0;
+  if (same_box) {
+    // Descriptor contents only: the device copy keeps its address.
+    HIPCHECK(c, hipMemcpyAsync(c->dinst, c->hinst.data(), c->hinst.size() * sizeof(InstDev),
+                               hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+  }
+  if ((st = upload(c, &c->dinst, c->hinst))) return st;
+  HIPCHECK(c, hipMemcpyAsync(c->dclock, &c->step, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  if (!was_mesh && (st = full_geometry(c, inst))) return st;
+  return rebuild_work(c);
+}
+
+}  // namespace
+
+extern "C" {
+
 lbm_status lbm_set_geometry(lbm_ctx* c, int inst, const lbm_body* body) {
   lbm_status st = check_inst(c, inst);
   if (st) return st;
@@ -864,8 +1186,7 @@ lbm_status lbm_set_geometry(lbm_ctx* c, int inst, const lbm_body* body) {
   if (body) b = *body;
   if (b.kind < LBM_BODY_NONE || b.kind > LBM_BODY_PLATES)
     return fail(c, LBM_ERR_INVALID, "unknown body kind %d", b.kind);
-  if (b.kind == LBM_BODY_MESH)
-    return fail(c, LBM_ERR_UNSUPPORTED, "surface-mesh bodies are not available in this build");
+  if (b.kind == LBM_BODY_MESH) return set_mesh(c, inst, b);
   if (b.kind == LBM_BODY_FLAP && c->D != 2) return fail(c, LBM_ERR_INVALID, "flap bodies are 2D only");
   for (int k = 0; k < 16; ++k)
     if (!std::isfinite(b.params[k])) return fail(c, LBM_ERR_INVALID, "non-finite body parameter");

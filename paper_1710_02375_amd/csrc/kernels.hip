@@ -53,6 +53,248 @@ __device__ __forceinline__ bool resolve_nb(const InstDev& I, int x, int y, int z
 }
 
 // ---------------------------------------------------------------------------
+// Surface-mesh bodies (Sec. II.C.1): solid test from the column crossings,
+// cut links by ray-face intersection over the face cells, velocities by
+// linear (barycentric) interpolation of the vertex velocities.  FP64.
+// ---------------------------------------------------------------------------
+// Solid when the line of the node's column crosses the surface an odd
+// number of times before x, or at x (surface points are solid).
+__device__ bool mesh_inside(const InstDev& I, int x, int y, int z) {
+  const int a = y - I.col_lo[0], b = z - I.col_lo[1];
+  if (a < 0 || b < 0 || a >= I.col_n[0] || b >= I.col_n[1]) return false;
+  const int k = a + I.col_n[0] * b;
+  const double xd = (double)x;
+  int below = 0;
+  for (int j = I.col_start[k]; j < I.col_start[k + 1]; ++j) {
+    const double xc = I.col_x[j];
+    if (xc == xd) return true;
+    if (xc < xd) ++below;
+  }
+  return (below & 1) != 0;
+}
+
+// Face cells meeting the box [lo, hi] (clamped to the grid): cell ranges.
+__device__ __forceinline__ void mesh_cells(const InstDev& I, const double (&lo)[3],
+                                           const double (&hi)[3], int (&c0)[3], int (&c1)[3]) {
+  for (int a = 0; a < 3; ++a) {
+    c0[a] = (int)floor((lo[a] - I.bin_lo[a]) / I.bin_h);
+    c1[a] = (int)floor((hi[a] - I.bin_lo[a]) / I.bin_h);
+    c0[a] = max(c0[a], 0);
+    c1[a] = min(c1[a], I.bin_n[a] - 1);
+  }
+}
+
+__device__ __forceinline__ void vel_at(const InstDev& I, int f, double l0, double l1, double l2,
+                                       double (&v)[3]) {
+  const int* fv = I.mesh_f + 3 * f;
+  for (int a = 0; a < 3; ++a)
+    v[a] = l0 * I.mesh_vel[3 * fv[0] + a] + l1 * I.mesh_vel[3 * fv[1] + a] +
+           (I.D == 3 ? l2 * I.mesh_vel[3 * fv[2] + a] : 0.0);
+}
+
+// Closest point of face f to p: squared distance and barycentric weights.
+// Triangles: the Voronoi region of p (a vertex, an edge or the interior)
+// from the signs of the projections on the edges; segments: the clamped
+// projection.
+__device__ double mesh_closest(const InstDev& I, int f, const double (&p)[3], double (&l)[3]) {
+  const int* fv = I.mesh_f + 3 * f;
+  const double* A = I.mesh_v + 3 * fv[0];
+  const double* B = I.mesh_v + 3 * fv[1];
+  if (I.D == 2) {
+    const double ex = B[0] - A[0], ey = B[1] - A[1];
+    const double len2 = ex * ex + ey * ey;
+    double s = len2 > 0.0 ? ((p[0] - A[0]) * ex + (p[1] - A[1]) * ey) / len2 : 0.0;
+    s = fmin(fmax(s, 0.0), 1.0);
+    const double dx = A[0] + s * ex - p[0], dy = A[1] + s * ey - p[1];
+    l[0] = 1.0 - s;
+    l[1] = s;
+    l[2] = 0.0;
+    return dx * dx + dy * dy;
+  }
+  const double* Cv = I.mesh_v + 3 * fv[2];
+  double ab[3], ac[3], ap[3];
+  for (int a = 0; a < 3; ++a) {
+    ab[a] = B[a] - A[a];
+    ac[a] = Cv[a] - A[a];
+    ap[a] = p[a] - A[a];
+  }
+  auto dot = [](const double* u, const double* v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; };
+  auto d2 = [&](double l0, double l1, double l2) {
+    double r = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double q = l0 * A[a] + l1 * B[a] + l2 * Cv[a] - p[a];
+      r += q * q;
+    }
+    return r;
+  };
+  const double d1 = dot(ab, ap), d2v = dot(ac, ap);
+  if (d1 <= 0.0 && d2v <= 0.0) {   // vertex A
+    l[0] = 1.0; l[1] = 0.0; l[2] = 0.0;
+    return d2(1.0, 0.0, 0.0);
+  }
+  double bp[3], cp[3];
+  for (int a = 0; a < 3; ++a) {
+    bp[a] = p[a] - B[a];
+    cp[a] = p[a] - Cv[a];
+  }
+  const double d3 = dot(ab, bp), d4 = dot(ac, bp);
+  if (d3 >= 0.0 && d4 <= d3) {   // vertex B
+    l[0] = 0.0; l[1] = 1.0; l[2] = 0.0;
+    return d2(0.0, 1.0, 0.0);
+  }
+  const double vc = d1 * d4 - d3 * d2v;
+  if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {   // edge AB
+    const double v = d1 / (d1 - d3);
+    l[0] = 1.0 - v; l[1] = v; l[2] = 0.0;
+    return d2(l[0], l[1], 0.0);
+  }
+  const double d5 = dot(ab, cp), d6 = dot(ac, cp);
+  if (d6 >= 0.0 && d5 <= d6) {   // vertex C
+    l[0] = 0.0; l[1] = 0.0; l[2] = 1.0;
+    return d2(0.0, 0.0, 1.0);
+  }
+  const double vb = d5 * d2v - d1 * d6;
+  if (vb <= 0.0 && d2v >= 0.0 && d6 <= 0.0) {   // edge AC
+    const double w = d2v / (d2v - d6);
+    l[0] = 1.0 - w; l[1] = 0.0; l[2] = w;
+    return d2(l[0], 0.0, w);
+  }
+  const double va = d3 * d6 - d5 * d4;
+  if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {   // edge BC
+    const double w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+    l[0] = 0.0; l[1] = 1.0 - w; l[2] = w;
+    return d2(0.0, l[1], w);
+  }
+  const double den = 1.0 / (va + vb + vc);   // interior
+  l[1] = vb * den;
+  l[2] = vc * den;
+  l[0] = 1.0 - l[1] - l[2];
+  return d2(l[0], l[1], l[2]);
+}
+
+// Velocity at the closest surface point to p: faces of the cells within two
+// spacings of p, all faces if none is there.
+__device__ void mesh_velocity(const InstDev& I, const double (&p)[3], double (&v)[3]) {
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = p[a] - 2.0;
+    hi[a] = p[a] + 2.0;
+  }
+  int c0[3], c1[3];
+  mesh_cells(I, lo, hi, c0, c1);
+  double best = 1e300, bl[3] = {1.0, 0.0, 0.0};
+  int bf = -1;
+  for (int cz_ = c0[2]; cz_ <= c1[2]; ++cz_)
+    for (int cy_ = c0[1]; cy_ <= c1[1]; ++cy_)
+      for (int cx_ = c0[0]; cx_ <= c1[0]; ++cx_) {
+        const int k = cx_ + I.bin_n[0] * (cy_ + I.bin_n[1] * cz_);
+        for (int j = I.bin_start[k]; j < I.bin_start[k + 1]; ++j) {
+          double l[3];
+          const double r = mesh_closest(I, I.bin_face[j], p, l);
+          if (r < best) {
+            best = r;
+            bf = I.bin_face[j];
+            bl[0] = l[0]; bl[1] = l[1]; bl[2] = l[2];
+          }
+        }
+      }
+  if (bf < 0) {
+    for (int f = 0; f < I.mesh_nf; ++f) {
+      double l[3];
+      const double r = mesh_closest(I, f, p, l);
+      if (r < best) {
+        best = r;
+        bf = f;
+        bl[0] = l[0]; bl[1] = l[1]; bl[2] = l[2];
+      }
+    }
+  }
+  v[0] = v[1] = v[2] = 0.0;
+  if (bf >= 0) vel_at(I, bf, bl[0], bl[1], bl[2], v);
+  if (I.D == 2) v[2] = 0.0;
+}
+
+// First surface point along the link from node p towards p - c: the
+// smallest t in [0, 1] at which p - t c meets a face (triangles:
+// Moller-Trumbore; segments: the 2x2 system), q = t, and the interpolated
+// velocity there.  Without a hit (the solid test and the intersection
+// disagree in the last bits) the wall is taken at the far node.
+__device__ void mesh_cut(const InstDev& I, int x, int y, int z, int c0, int c1, int c2,
+                         double& q, double (&uw)[3]) {
+  const double p[3] = {(double)x, (double)y, (double)z};
+  const double dir[3] = {-(double)c0, -(double)c1, -(double)c2};
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = fmin(p[a], p[a] + dir[a]) - 1e-9;
+    hi[a] = fmax(p[a], p[a] + dir[a]) + 1e-9;
+  }
+  int cl[3], ch[3];
+  mesh_cells(I, lo, hi, cl, ch);
+  const double tol = 1e-12;
+  double tbest = 2.0, bl[3] = {1.0, 0.0, 0.0};
+  int bf = -1;
+  for (int kz = cl[2]; kz <= ch[2]; ++kz)
+    for (int ky = cl[1]; ky <= ch[1]; ++ky)
+      for (int kx = cl[0]; kx <= ch[0]; ++kx) {
+        const int k = kx + I.bin_n[0] * (ky + I.bin_n[1] * kz);
+        for (int j = I.bin_start[k]; j < I.bin_start[k + 1]; ++j) {
+          const int f = I.bin_face[j];
+          const int* fv = I.mesh_f + 3 * f;
+          const double* A = I.mesh_v + 3 * fv[0];
+          const double* B = I.mesh_v + 3 * fv[1];
+          double t, l1, l2;
+          if (I.D == 3) {
+            const double* Cv = I.mesh_v + 3 * fv[2];
+            const double e1[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+            const double e2[3] = {Cv[0] - A[0], Cv[1] - A[1], Cv[2] - A[2]};
+            const double pv[3] = {dir[1] * e2[2] - dir[2] * e2[1], dir[2] * e2[0] - dir[0] * e2[2],
+                                  dir[0] * e2[1] - dir[1] * e2[0]};
+            const double det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
+            if (fabs(det) < 1e-300) continue;
+            const double id = 1.0 / det;
+            const double tv[3] = {p[0] - A[0], p[1] - A[1], p[2] - A[2]};
+            l1 = (tv[0] * pv[0] + tv[1] * pv[1] + tv[2] * pv[2]) * id;
+            if (l1 < -tol || l1 > 1.0 + tol) continue;
+            const double qv[3] = {tv[1] * e1[2] - tv[2] * e1[1], tv[2] * e1[0] - tv[0] * e1[2],
+                                  tv[0] * e1[1] - tv[1] * e1[0]};
+            l2 = (dir[0] * qv[0] + dir[1] * qv[1] + dir[2] * qv[2]) * id;
+            if (l2 < -tol || l1 + l2 > 1.0 + tol) continue;
+            t = (e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2]) * id;
+          } else {
+            // p + t dir = A + s (B - A): Cramer's rule on the 2x2 system.
+            const double ex = B[0] - A[0], ey = B[1] - A[1];
+            const double det = ex * dir[1] - ey * dir[0];
+            if (fabs(det) < 1e-300) continue;
+            const double rx = p[0] - A[0], ry = p[1] - A[1];
+            const double sg = (rx * dir[1] - ry * dir[0]) / det;
+            if (sg < -tol || sg > 1.0 + tol) continue;
+            t = (rx * ey - ry * ex) / det;
+            l1 = sg;
+            l2 = 0.0;
+          }
+          if (t < -1e-9 || t > 1.0 + 1e-9) continue;
+          if (t < tbest) {
+            tbest = t;
+            bf = f;
+            bl[0] = 1.0 - l1 - l2;
+            bl[1] = l1;
+            bl[2] = l2;
+          }
+        }
+      }
+  if (bf >= 0) {
+    q = fmin(fmax(tbest, 1e-12), 1.0);
+    for (int a = 0; a < 3; ++a) bl[a] = fmin(fmax(bl[a], 0.0), 1.0);
+    vel_at(I, bf, bl[0], bl[1], bl[2], uw);
+    if (I.D == 2) uw[2] = 0.0;
+  } else {
+    q = 1.0;
+    const double pf[3] = {p[0] + dir[0], p[1] + dir[1], p[2] + dir[2]};
+    mesh_velocity(I, pf, uw);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Prescribed-motion bodies (FP64).  Time t is the step count.
 // ---------------------------------------------------------------------------
 __device__ bool body_inside(const InstDev& I, double x, double y, double z, double t) {
@@ -75,6 +317,8 @@ __device__ bool body_inside(const InstDev& I, double x, double y, double z, doub
       const double xc = p[0] + p[3] * sin(p[4] * t + p[5]) * (sl / p[1]) * (sl / p[1]);
       return fabs(x - xc) <= 0.5 * p[2];
     }
+    case LBM_BODY_MESH:
+      return mesh_inside(I, (int)x, (int)y, (int)z);
     case LBM_BODY_PLATES:
       return y < p[0] || y > p[1];
     default:
@@ -98,6 +342,11 @@ __device__ void body_velocity(const InstDev& I, double x, double y, double z, do
       v[0] = p[3] * p[4] * cos(p[4] * t + p[5]) * (sl / p[1]) * (sl / p[1]);
       break;
     }
+    case LBM_BODY_MESH: {
+      const double pt[3] = {x, y, z};
+      mesh_velocity(I, pt, v);
+      break;
+    }
     case LBM_BODY_PLATES: {
       const double* u = (y < 0.5 * (p[0] + p[1])) ? &p[2] : &p[5];
       for (int a = 0; a < I.D; ++a) v[a] = u[a];
@@ -114,6 +363,10 @@ __device__ void body_velocity(const InstDev& I, double x, double y, double z, do
 // bisection to the first inside point.
 __device__ void body_cut(const InstDev& I, int x, int y, int z, int c0, int c1, int c2, double t,
                          double& q, double (&uw)[3]) {
+  if (I.body_kind == LBM_BODY_MESH) {
+    mesh_cut(I, x, y, z, c0, c1, c2, q, uw);
+    return;
+  }
   if (I.body_kind == LBM_BODY_SPHERE) {
     const double* p = I.body;
     const double s = sin(p[7] * t + p[8]);

@@ -181,6 +181,28 @@ struct InstDev {
   double u_in[3];
   double body[16];
   int box_lo[3], box_hi[3];   // swept box of the body
+  // Surface mesh (body_kind LBM_BODY_MESH), device arrays of the context:
+  // vertices and their velocities (3 doubles each), faces (3 vertex indices
+  // each; in 2D segments of the first two).
+  const double* mesh_v;
+  const double* mesh_vel;
+  const int* mesh_f;
+  int mesh_nf;
+  // Crossings of the lattice lines along x with the surface: the line of
+  // column (y, z) = (col_lo[0] + a, col_lo[1] + b), a < col_n[0], b < col_n[1],
+  // k = a + col_n[0] b, crosses at x = col_x[col_start[k] .. col_start[k+1]),
+  // ascending.  Lines outside the columns do not meet the surface.
+  const int* col_start;
+  const double* col_x;
+  int col_lo[2], col_n[2];
+  // Faces by cell of a uniform grid (cell size bin_h from bin_lo, bin_n cells
+  // per axis): cell k = a + bin_n[0] (b + bin_n[1] c) lists the faces whose
+  // bounding box meets it, bin_face[bin_start[k] .. bin_start[k+1]).
+  const int* bin_start;
+  const int* bin_face;
+  double bin_lo[3];
+  double bin_h;
+  int bin_n[3];
 };
 
 // A contiguous run of nodes of one instance, processed by one workgroup.
