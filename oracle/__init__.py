@@ -79,6 +79,13 @@ def lib():
         L.orc_set_time.argtypes = [C.c_void_p, C.c_long]
         L.orc_set_mesh.argtypes = [C.c_void_p, C.c_int, _dp, _dp, C.c_int, _ip]
         L.orc_body_velocity.argtypes = [C.c_void_p, _dp, C.c_double, _dp]
+        L.orc_collide_forced.argtypes = [C.c_int, C.c_double, C.c_int, C.c_int, _dp, _dp, _dp,
+                                         C.POINTER(C.c_double)]
+        L.orc_eos_pressure.restype = C.c_double
+        L.orc_eos_pressure.argtypes = [C.c_double]
+        L.orc_set_multiphase.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double]
+        L.orc_mp_force.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_mp_last_force.argtypes = [C.c_void_p, _dp]
         _lib = L
     return _lib
 
@@ -127,6 +134,24 @@ def collide(Q, beta, f, collision=0, trace_in_s=0):
     st = lib().orc_collide(Q, float(beta), int(collision), int(trace_in_s), _f64(f), out,
                            C.byref(g))
     return out, g.value, st
+
+
+def collide_forced(Q, beta, f, F, collision=0, trace_in_s=0):
+    """Forced KBC collision of Sec. III.B (exact difference method, gamma from
+    the scalar product shifted to f^eq(rho, u + F/rho)); returns (f', gamma,
+    status)."""
+    out = np.zeros(Q)
+    FF = np.zeros(3)
+    FF[: len(F)] = F
+    g = C.c_double(0.0)
+    st = lib().orc_collide_forced(Q, float(beta), int(collision), int(trace_in_s), _f64(f), FF,
+                                  out, C.byref(g))
+    return out, g.value, st
+
+
+def eos_pressure(rho):
+    """Non-ideal pressure p(rho) of Sec. III.B, Eq. eos."""
+    return lib().orc_eos_pressure(float(rho))
 
 
 def grad_fstar(Q, rho, v, Pi):
@@ -295,6 +320,24 @@ class Domain:
         v = np.zeros(3)
         lib().orc_body_velocity(self._h, xx, float(self.time if t is None else t), v)
         return v
+
+    def set_multiphase(self, kappa, kappa_w=0.0, on=True):
+        """Multiphase forcing of Sec. III.B (faces periodic or walls only)."""
+        if lib().orc_set_multiphase(self._h, int(bool(on)), float(kappa), float(kappa_w)) != 0:
+            raise ValueError("oracle: multiphase needs periodic or wall faces")
+
+    def mp_force(self, rho):
+        """Body force of Sec. III.B for density field rho (N,) over the
+        current geometry; (D, N)."""
+        out = np.zeros(3 * self.N)
+        lib().orc_mp_force(self._h, _f64(np.asarray(rho).reshape(-1)), out)
+        return out.reshape(3, self.N)[: self.D]
+
+    def mp_last_force(self):
+        """Body force the last multiphase step used; (D, N)."""
+        out = np.zeros(3 * self.N)
+        assert lib().orc_mp_last_force(self._h, out) == 0
+        return out.reshape(3, self.N)[: self.D]
 
     def set_time(self, t):
         """Sets the step count of the stored state (then call set_body)."""

@@ -20,8 +20,12 @@
 // a density other than 1) and by prepared lagged fields on which each target
 // formula is exact (linear fallback, central difference, quadratic wall
 // differences, two cut sides); the probe fallback of the wall stress by
-// brute force and by a wall probe in developed Poiseuille flow.  Planted
-// mistakes in a copy of this file fail those pins.
+// brute force and by a wall probe in developed Poiseuille flow.  The
+// multiphase step (Sec. III.B) is pinned by fields on which its derivative
+// stencils are exact, closed-form wetting sums at walls and bodies, the
+// invariants of the forced collision, and the coexisting liquid and vapour
+// densities of a flat interface that the paper prints for its equation of
+// state.  Planted mistakes in a copy of this file fail those pins.
 //
 // Lattice conventions: velocities c_i in {-1,0,1}^D with index
 // i = (cx+1) + 3(cy+1) + 9(cz+1), opposite direction Q-1-i, weights the tensor
@@ -240,6 +244,74 @@ int collide(const Lattice& L, double beta, int collision, int trace_in_s, const 
   if (feq_out)
     for (int i = 0; i < Q; ++i) feq_out[i] = feq[i];
   return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Forced KBC collision (Sec. III.B, Eq. force_mp and the shifted scalar
+// product); pinned: gamma as the exact minimiser of the quadratic entropy norm
+// about the shifted equilibrium, the momentum gain F, the LBGK limit.
+// The force enters by the exact difference method: the velocity increment is
+// du = F / rho (unit time step) and the post-collision state gains
+// f^eq(rho, u + du) - f^eq(rho, u).  Delta s and Delta h are taken about
+// f^eq(rho, u) as in the unforced collision; the stabiliser gamma uses the
+// scalar product with weights 1 / f^eq(rho, u + du).
+// Returns 0 on success, 1 for an invalid state (rho <= 0, |u_a| >= 1 or
+// |u_a + du_a| >= 1, or not finite), in which case fout = f.
+// ---------------------------------------------------------------------------
+int collide_forced(const Lattice& L, double beta, int collision, int trace_in_s, const double* f,
+                   const double* F, double* fout, double* gamma_out) {
+  const int Q = L.Q;
+  double rho, u[3];
+  moments(L, f, &rho, u);
+  double us[3];
+  bool ok = std::isfinite(rho) && rho > 0.0;
+  for (int a = 0; a < 3; ++a) {
+    us[a] = u[a] + F[a] / rho;
+    ok = ok && std::isfinite(u[a]) && std::fabs(u[a]) < 1.0 && std::isfinite(us[a]) &&
+         std::fabs(us[a]) < 1.0;
+  }
+  if (!ok) {
+    for (int i = 0; i < Q; ++i) fout[i] = f[i];
+    if (gamma_out) *gamma_out = 2.0;
+    return 1;
+  }
+  double feq[27], feqs[27], delta[27], ds[27], dh[27];
+  equilibrium(L, rho, u, feq);
+  equilibrium(L, rho, us, feqs);
+  for (int i = 0; i < Q; ++i) delta[i] = f[i] - feq[i];
+  split(L, delta, trace_in_s, ds, dh);
+  double gamma = 2.0;
+  if (collision == 0) {
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < Q; ++i) {
+      a += ds[i] * dh[i] / feqs[i];
+      b += dh[i] * dh[i] / feqs[i];
+    }
+    if (b != 0.0) gamma = 1.0 / beta - (2.0 - 1.0 / beta) * a / b;
+  }
+  for (int i = 0; i < Q; ++i)
+    fout[i] = f[i] - beta * (2.0 * ds[i] + gamma * dh[i]) + (feqs[i] - feq[i]);
+  if (gamma_out) *gamma_out = gamma;
+  return 0;
+}
+
+// Non-ideal equation of state (Sec. III.B, Eq. eos): a sixth-degree
+// polynomial in rho with the printed coefficients (pinned: the coexisting
+// densities of a flat interface).
+double eos_pressure(double rho) {
+  static const double a[7] = {0.0,
+                              5.3e-2,
+                              -3.818183621928911e-2,
+                              4.139745482116095e-3,
+                              3.748484095210317e-4,
+                              -1.4552652965531227e-4,
+                              1.2746947442749278e-5};
+  double p = 0.0, r = 1.0;
+  for (int k = 1; k <= 6; ++k) {
+    r *= rho;
+    p += a[k] * r;
+  }
+  return p;
 }
 
 // ---------------------------------------------------------------------------
@@ -546,6 +618,12 @@ struct Domain {
   long gamma_count = 0;
   long invalid_nodes = 0;
   int nthreads = 0;
+  // Multiphase forcing (Sec. III.B): on/off, surface-tension and wetting
+  // coefficients, and the force of the last step at every node (3N, zero at
+  // solid nodes).
+  int mp = 0;
+  double kappa = 0.0, kappa_w = 0.0;
+  std::vector<double> mp_force;
 };
 
 inline long node_index(const Domain& d, int x, int y, int z) {
@@ -779,6 +857,72 @@ void grad_targets(const Domain& d, const int* x, long n, const double* f, const 
   *rho_t_out = rho_t;
 }
 
+// ---------------------------------------------------------------------------
+// Multiphase body force (Sec. III.B, Eqs. Force, force1, Korteweg, force2 and
+// the wetting force); pinned: exact on prepared fields (linear phi, cubic rho,
+// flat walls) and the coexisting densities of a flat interface.
+//   F = 2 phi grad(phi) + kappa rho grad(lap rho) + kappa_w rho sum_i W_i s(x + c_i) c_i,
+//   phi = sqrt(rho cs^2 - p(rho)).
+// The sign of the kappa term is the one Eqs. force1 and Korteweg give: the
+// divergence of the Korteweg tensor reduces to grad p - kappa rho grad(lap rho).
+// Derivatives use the lattice stencils (cs^2 = 1/3)
+//   d_a X = (1/cs^2) sum_i W_i c_ia X(x + c_i),
+//   lap X = (2/cs^2) sum_i W_i (X(x + c_i) - X(x)),
+// grad(lap rho) being the first applied to the second.  A neighbour that is
+// not a fluid node (solid, or beyond a wall face) contributes the node's own
+// value, and counts s = 1 in the wetting sum, whose weights are the lattice
+// weights.  rho: N values (not read at solid nodes); F: 3N (x, y, z per
+// node), zero at solid nodes.
+// ---------------------------------------------------------------------------
+void mp_forces(const Domain& d, const std::vector<uint8_t>& solid, const double* rho, double* F) {
+  const Lattice& L = *d.L;
+  const int Q = L.Q, D = L.D;
+  const long N = d.N;
+  std::vector<double> phi(N, 0.0), lap(N, 0.0);
+  for (long n = 0; n < N; ++n)
+    if (!solid[n]) phi[n] = std::sqrt(rho[n] / 3.0 - eos_pressure(rho[n]));
+  // Whether x + c_i is a fluid node, and its index.
+  auto fluid_nb = [&](const int* x, int i, long* m) -> bool {
+    return resolve(d, x, L.c[i], false, m) == LINK_NODE && !solid[*m];
+  };
+#pragma omp parallel for schedule(static) num_threads(d.nthreads)
+  for (long n = 0; n < N; ++n) {
+    if (solid[n]) continue;
+    int x[3];
+    coords(d, n, x);
+    double s = 0.0;
+    for (int i = 0; i < Q; ++i) {
+      long m;
+      const double v = fluid_nb(x, i, &m) ? rho[m] : rho[n];
+      s += L.w[i] * (v - rho[n]);
+    }
+    lap[n] = 6.0 * s;
+  }
+#pragma omp parallel for schedule(static) num_threads(d.nthreads)
+  for (long n = 0; n < N; ++n) {
+    double* Fn = F + 3 * n;
+    Fn[0] = Fn[1] = Fn[2] = 0.0;
+    if (solid[n]) continue;
+    int x[3];
+    coords(d, n, x);
+    double gphi[3] = {0.0, 0.0, 0.0}, glap[3] = {0.0, 0.0, 0.0}, wet[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+      long m;
+      const bool fl = fluid_nb(x, i, &m);
+      const double vp = fl ? phi[m] : phi[n];
+      const double vl = fl ? lap[m] : lap[n];
+      for (int a = 0; a < D; ++a) {
+        gphi[a] += L.w[i] * L.c[i][a] * vp;
+        glap[a] += L.w[i] * L.c[i][a] * vl;
+        if (!fl) wet[a] += L.w[i] * L.c[i][a];
+      }
+    }
+    for (int a = 0; a < D; ++a)
+      Fn[a] = 2.0 * phi[n] * (3.0 * gphi[a]) + d.kappa * rho[n] * (3.0 * glap[a]) +
+              d.kappa_w * rho[n] * wet[a];
+  }
+}
+
 // Steps 1 and 2 of a time step n -> n+1: geometry at t_{n+1} (solid_new),
 // lagged moments rho_n, u_n of the stored state, and the fresh-node refill
 // (nodes solid at n and fluid at n+1): A := f^eq(rho_bar, u_body) with rho_bar
@@ -840,8 +984,9 @@ void prepare_step(Domain& d, std::vector<uint8_t>& solid_new, std::vector<double
 
 // One time step n -> n+1 (pull form of Eq. (1)):
 //   1 geometry at t_{n+1};  2 fresh-node refill;  3 streaming;
-//   4 Grad fill of missing populations;  5 inflow/outflow override;  6 collision;
-//   7 optional storage rounding.
+//   4 Grad fill of missing populations;  5 inflow/outflow override;
+//   (multiphase: the body force from the densities of the state after 3-5);
+//   6 collision (forced in multiphase);  7 optional storage rounding.
 void step_once(Domain& d) {
   const Lattice& L = *d.L;
   const int Q = L.Q, D = L.D;
@@ -904,6 +1049,20 @@ void step_once(Domain& d) {
     }
   }
 
+  // Multiphase: density of every fluid node after streaming and the boundary
+  // fill, then the body force of Sec. III.B from those densities.
+  if (d.mp) {
+    std::vector<double> rho_pre(N, 0.0);
+    for (long n = 0; n < N; ++n) {
+      if (solid_new[n]) continue;
+      double r = 0.0;
+      for (int i = 0; i < Q; ++i) r += F[n * Q + i];
+      rho_pre[n] = r;
+    }
+    d.mp_force.assign((size_t)3 * N, 0.0);
+    mp_forces(d, solid_new, rho_pre.data(), d.mp_force.data());
+  }
+
   // 6. Collision at every fluid node.
   double gmin = 1e300, gmax = -1e300, gsum = 0.0;
   long gcnt = 0, bad = 0;
@@ -912,7 +1071,11 @@ void step_once(Domain& d) {
   for (long n = 0; n < N; ++n) {
     if (solid_new[n]) continue;
     double g;
-    bad += collide(L, d.beta, d.collision, d.trace_in_s, &F[n * Q], &d.A[n * Q], &g);
+    if (d.mp)
+      bad += collide_forced(L, d.beta, d.collision, d.trace_in_s, &F[n * Q], &d.mp_force[3 * n],
+                            &d.A[n * Q], &g);
+    else
+      bad += collide(L, d.beta, d.collision, d.trace_in_s, &F[n * Q], &d.A[n * Q], &g);
     gmin = std::min(gmin, g);
     gmax = std::max(gmax, g);
     gsum += g;
@@ -1035,6 +1198,14 @@ int orc_collide(int Q, double beta, int collision, int trace_in_s, const double*
   if (Q != 9 && Q != 27) return -1;
   return collide(lattice(Q), beta, collision, trace_in_s, f, fout, gamma);
 }
+
+int orc_collide_forced(int Q, double beta, int collision, int trace_in_s, const double* f,
+                       const double* F, double* fout, double* gamma) {
+  if (Q != 9 && Q != 27) return -1;
+  return collide_forced(lattice(Q), beta, collision, trace_in_s, f, F, fout, gamma);
+}
+
+double orc_eos_pressure(double rho) { return eos_pressure(rho); }
 
 int orc_grad_fstar(int Q, double rho, const double* v, const double* Pi, double* out) {
   if (Q != 9 && Q != 27) return -1;
@@ -1229,6 +1400,39 @@ int orc_set_mesh(void* h, int nv, const double* verts, const double* vel, int nt
     coords(*d, n, x);
     d->solid[n] = inside_at(*d, x, t) ? 1 : 0;
   }
+  return 0;
+}
+
+// Multiphase forcing (Sec. III.B) on or off, with surface-tension
+// coefficient kappa and wetting coefficient kappa_w.  Faces must be periodic
+// or walls (-1 otherwise).
+int orc_set_multiphase(void* h, int on, double kappa, double kappa_w) {
+  Domain* d = static_cast<Domain*>(h);
+  for (int k = 0; k < 6; ++k)
+    if (on && d->face[k] != PERIODIC && d->face[k] != WALL) return -1;
+  d->mp = on ? 1 : 0;
+  d->kappa = kappa;
+  d->kappa_w = kappa_w;
+  return 0;
+}
+
+// Body force of Sec. III.B for a given density field (N values) over the
+// current geometry; F planar [a * N + node], zero at solid nodes.
+int orc_mp_force(void* h, const double* rho, double* F) {
+  const Domain* d = static_cast<const Domain*>(h);
+  std::vector<double> f3((size_t)3 * d->N, 0.0);
+  mp_forces(*d, d->solid, rho, f3.data());
+  for (long n = 0; n < d->N; ++n)
+    for (int a = 0; a < 3; ++a) F[a * d->N + n] = f3[3 * n + a];
+  return 0;
+}
+
+// Body force used by the last multiphase step, planar as above.
+int orc_mp_last_force(void* h, double* F) {
+  const Domain* d = static_cast<const Domain*>(h);
+  if (d->mp_force.size() != (size_t)3 * d->N) return -1;
+  for (long n = 0; n < d->N; ++n)
+    for (int a = 0; a < 3; ++a) F[a * d->N + n] = d->mp_force[3 * n + a];
   return 0;
 }
 

@@ -1,7 +1,8 @@
-"""The oracle's boundary pins are strong enough to catch plausible mistakes.
+"""The oracle's pins are strong enough to catch plausible mistakes.
 
 Each case copies the oracle source, plants one mistake in a boundary formula
-(Sec. II.C.1 Grad target values and fresh-node fill, Sec. II.C.2 wall stress),
+(Sec. II.C.1 Grad target values and fresh-node fill, Sec. II.C.2 wall stress,
+surface meshes) or in the multiphase step (Sec. III.B),
 builds the copy in a temporary directory and runs one domain pin against it in
 a child process; the pin must fail.  Nothing here touches the GPU path.
 """
@@ -116,6 +117,43 @@ CASES = [
      "      const double s = A > 0.0 ? clamp01(-Dv / A) : 0.0;",
      "      const double s = A > 0.0 ? -Dv / A : 0.0;",
      "test_oracle_mesh:test_mesh_velocity_at_closest_point_of_a_box", ()),
+    # Korteweg term with the sign printed in the paper's reduced form.
+    ("mp_kappa_sign",
+     "2.0 * phi[n] * (3.0 * gphi[a]) + d.kappa * rho[n] * (3.0 * glap[a]) +",
+     "2.0 * phi[n] * (3.0 * gphi[a]) - d.kappa * rho[n] * (3.0 * glap[a]) +",
+     "test_oracle_multiphase:test_flat_interface_coexistence_matches_printed", (9,)),
+    # phi gradient stencil without the 1 / cs^2 factor.
+    ("mp_gradient_factor",
+     "2.0 * phi[n] * (3.0 * gphi[a])", "2.0 * phi[n] * (1.0 * gphi[a])",
+     "test_oracle_multiphase:test_phi_gradient_term_exact_on_linear_phi", (27,)),
+    # Laplacian stencil with the factor 1 / cs^2 instead of 2 / cs^2.
+    ("mp_laplacian_factor",
+     "    lap[n] = 6.0 * s;", "    lap[n] = 3.0 * s;",
+     "test_oracle_multiphase:test_korteweg_term_exact_on_cubic_density", (9,)),
+    # Non-fluid neighbour read as zero density instead of the node's own.
+    ("mp_solid_neighbour_zero",
+     "      const double v = fluid_nb(x, i, &m) ? rho[m] : rho[n];",
+     "      const double v = fluid_nb(x, i, &m) ? rho[m] : 0.0;",
+     "test_oracle_multiphase:test_wetting_force_flat_wall_and_corner", (9,)),
+    # Wetting sum over the fluid neighbours instead of the solid ones.
+    ("mp_wetting_fluid_set",
+     "        if (!fl) wet[a] += L.w[i] * L.c[i][a];",
+     "        if (fl) wet[a] += L.w[i] * L.c[i][a];",
+     "test_oracle_multiphase:test_wetting_force_at_a_body", ()),
+    # EOS with one coefficient's sign flipped.
+    ("mp_eos_coefficient",
+     "                              4.139745482116095e-3,",
+     "                              -4.139745482116095e-3,",
+     "test_oracle_multiphase:test_flat_interface_coexistence_matches_printed", (9,)),
+    # Stabiliser from the unshifted scalar product.
+    ("mp_gamma_unshifted",
+     "      a += ds[i] * dh[i] / feqs[i];\n      b += dh[i] * dh[i] / feqs[i];",
+     "      a += ds[i] * dh[i] / feq[i];\n      b += dh[i] * dh[i] / feq[i];",
+     "test_oracle_multiphase:test_shifted_gamma_minimises_shifted_entropy_norm", (27,)),
+    # Exact difference method with half the velocity increment.
+    ("mp_edm_half_increment",
+     "    us[a] = u[a] + F[a] / rho;", "    us[a] = u[a] + 0.5 * F[a] / rho;",
+     "test_oracle_multiphase:test_forced_step_keeps_mass_and_adds_force", (9,)),
 ]
 
 CHILD = textwrap.dedent("""
