@@ -221,6 +221,32 @@ lbm_status lbm_wall_force(lbm_ctx* ctx, int inst, const double* xq, const double
 lbm_status lbm_wall_force_noalloc(lbm_ctx* ctx, int inst, const double* xq, const double* nq,
                                   const double* wq, int n_q, double* traction, double force[3]);
 
+/* Multiphase KBC (Sec. III.B) on instance inst (enable != 0) or off.  Each
+ * step then adds the body force
+ *   F = 2 phi grad(phi) + kappa rho grad(lap rho) + kappa_w rho sum_i W_i s(x + c_i) c_i,
+ *   phi = sqrt(rho/3 - p(rho)),  p(rho) the sixth-degree polynomial of Eq. eos,
+ * from the densities of the state after streaming and the boundary fill
+ * (Eqs. Force, force1, Korteweg, force2; the kappa term with the sign that the
+ * divergence of the Korteweg tensor gives).  Derivatives use the
+ * lattice-weight stencils grad_a X = 3 sum_i W_i c_ia X(x + c_i) and
+ * lap X = 6 sum_i W_i (X(x + c_i) - X(x)); a neighbour that is solid or
+ * beyond a wall face gives the node's own value and counts s = 1 in the
+ * wetting sum.  The force enters by the exact difference method (Eq.
+ * force_mp): the post-collision state gains f^eq(rho, u + F/rho) -
+ * f^eq(rho, u); gamma uses the scalar product weighted by
+ * 1 / f^eq(rho, u + F/rho).  The collision runs in FP64.  kappa sets the
+ * surface tension, kappa_w the wetting (negative: non-wetting); this
+ * discretisation is stable for kappa rho_liquid below about 0.3.
+ * While any instance of the context has it on, every instance steps through
+ * the multiphase kernels (those with it off at zero force) and stores
+ * moments that include the force (lbm_moments reports j = rho u + F).
+ * Needs FP64 or FP32 storage and periodic or wall faces
+ * (LBM_ERR_UNSUPPORTED otherwise); lbm_wall_force returns
+ * LBM_ERR_UNSUPPORTED for a multiphase instance.  The first call that
+ * enables it allocates 3 fields of N values (FP64 for FP64 storage, else
+ * FP32) for all instances.  Synchronous. */
+lbm_status lbm_set_multiphase(lbm_ctx* ctx, int inst, int enable, double kappa, double kappa_w);
+
 /* Checkpoint: copies the populations of instance inst to / from the host
  * (Q*N doubles, population-major, full f_i).  A set is rounded to the
  * storage format.  Resuming from get -> set is bitwise exact. */

@@ -65,6 +65,12 @@ struct lbm_ctx {
     int* bf = nullptr;     size_t bf_cap = 0;   // cell faces
   };
   std::vector<MeshBuf> mesh;
+  // Multiphase (Sec. III.B): the fields of every instance (density, phi,
+  // Laplacian; 3 N elements each, FP64 for FP64 storage, else FP32), and
+  // whether some instance has the forcing on (then every instance steps
+  // through the multiphase pipeline, those with it off at zero force).
+  void* mp_field = nullptr;
+  bool any_mp = false;
   double* force_ws = nullptr;     // wall-force workspace, grown on demand
   size_t force_ws_doubles = 0;
   double* scratch = nullptr;      // device address of `scratch` on this device
@@ -471,20 +477,36 @@ lbm_status enqueue_step(lbm_ctx* c, int src) {
                                    c->flags, c->dclock, 1, c->stream));
   const int ntiles = (int)c->tiles.size();
   const int nbt = (int)c->btiles.size();
+  // Multiphase: the boundary kernels write pre-collision states, then the
+  // three multiphase passes stream, differentiate and collide.
+  const bool mp = c->any_mp;
   if (c->launch_mode == 0) {
     HIPCHECK(c, c->ops->boundary(b, c->dregions, c->dbtiles, 0, nbt, c->dblist, c->bl_total,
                                  c->dbcount + 2 * c->n_inst, c->bl_nwg_all, c->bl_nwall_all, ntiles,
-                                 c->stream));
-    HIPCHECK(c, c->ops->bulk(c->variant, b, c->dtiles, 0, ntiles, c->any_faces, c->stream));
+                                 mp, c->stream));
+    if (mp) {
+      for (int stage = 0; stage < 3; ++stage)
+        HIPCHECK(c, c->ops->mp(stage, b, c->dtiles, 0, ntiles, c->stream));
+    } else {
+      HIPCHECK(c, c->ops->bulk(c->variant, b, c->dtiles, 0, ntiles, c->any_faces, c->stream));
+    }
   } else {
     for (int k = 0; k < c->n_inst; ++k) {
       HIPCHECK(c, c->ops->boundary(b, c->dregions, c->dbtiles, c->bt_first[k], c->bt_count[k],
                                    c->dblist + 2 * (size_t)c->bl_off[k], c->bl_cap[k],
                                    c->dbcount + 2 * k, c->bl_nwg[k], c->bl_nwall[k],
-                                   ntiles + c->bl_stat[k], c->stream));
-      HIPCHECK(c, c->ops->bulk(c->variant, b, c->dtiles, c->tile_first[k], c->tile_count[k],
-                               c->has_faces[k] != 0, c->stream));
+                                   ntiles + c->bl_stat[k], mp, c->stream));
+      if (!mp)
+        HIPCHECK(c, c->ops->bulk(c->variant, b, c->dtiles, c->tile_first[k], c->tile_count[k],
+                                 c->has_faces[k] != 0, c->stream));
     }
+    // The multiphase passes read neighbouring fields, which the boundary
+    // kernels of every instance write first.
+    if (mp)
+      for (int stage = 0; stage < 3; ++stage)
+        for (int k = 0; k < c->n_inst; ++k)
+          HIPCHECK(c, c->ops->mp(stage, b, c->dtiles, c->tile_first[k], c->tile_count[k],
+                                 c->stream));
   }
   HIPCHECK(c, c->ops->fixup(b, kFixupBlocks, ntiles + c->bstat_slots, c->stream));
   return LBM_OK;
@@ -816,6 +838,7 @@ lbm_status lbm_destroy(lbm_ctx* c) {
   dev_free(c, c->dgtiles);
   dev_free(c, c->dstats);
   dev_free(c, c->force_ws);
+  dev_free(c, c->mp_field);
   for (auto& m : c->mesh) {
     dev_free(c, m.v);
     dev_free(c, m.f);
@@ -1222,6 +1245,42 @@ lbm_status lbm_set_geometry(lbm_ctx* c, int inst, const lbm_body* body) {
   return LBM_OK;
 }
 
+lbm_status lbm_set_multiphase(lbm_ctx* c, int inst, int enable, double kappa, double kappa_w) {
+  lbm_status st = check_inst(c, inst);
+  if (st) return st;
+  if (enable) {
+    if (c->storage != LBM_F64 && c->storage != LBM_F32)
+      return fail(c, LBM_ERR_UNSUPPORTED, "multiphase needs FP64 or FP32 storage");
+    if (!std::isfinite(kappa) || !std::isfinite(kappa_w))
+      return fail(c, LBM_ERR_INVALID, "non-finite multiphase coefficient");
+    for (int k = 0; k < 6; ++k)
+      if (c->hinst[inst].face[k] != LBM_FACE_PERIODIC && c->hinst[inst].face[k] != LBM_FACE_WALL)
+        return fail(c, LBM_ERR_UNSUPPORTED, "multiphase needs periodic or wall faces");
+  }
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  const size_t fsz = c->storage == LBM_F64 ? sizeof(double) : sizeof(float);
+  if (enable && !c->mp_field) {
+    if ((st = dev_alloc(c, 3 * (size_t)c->total_nodes * fsz, &c->mp_field))) return st;
+    HIPCHECK(c, hipMemsetAsync(c->mp_field, 0, 3 * (size_t)c->total_nodes * fsz, c->stream));
+  }
+  InstDev& I = c->hinst[inst];
+  I.mp = enable ? 1 : 0;
+  I.mp_kappa = enable ? kappa : 0.0;
+  I.mp_kappa_w = enable ? kappa_w : 0.0;
+  bool any = false;
+  for (int k = 0; k < c->n_inst; ++k) any = any || c->hinst[k].mp;
+  int64_t off = 0;
+  for (int k = 0; k < c->n_inst; ++k) {
+    c->hinst[k].mp_field = any ? static_cast<char*>(c->mp_field) + 3 * (size_t)off * fsz : nullptr;
+    off += c->hinst[k].N;
+  }
+  c->any_mp = any;
+  if ((st = upload(c, &c->dinst, c->hinst))) return st;
+  invalidate_graphs(c);
+  c->force_valid[inst] = 0;
+  return LBM_OK;
+}
+
 lbm_status lbm_step(lbm_ctx* c, int n_steps) {
   if (!c) return LBM_ERR_INVALID;
   if (n_steps < 0) return fail(c, LBM_ERR_INVALID, "n_steps < 0");
@@ -1392,6 +1451,8 @@ lbm_status wall_force_args(lbm_ctx* c, int inst, const double* xq, const double*
     return fail(c, LBM_ERR_INVALID, "bad quadrature arguments");
   if (!c->force_valid[inst])
     return fail(c, LBM_ERR_INVALID, "wall force needs a step after the last geometry or state change");
+  if (c->hinst[inst].mp)
+    return fail(c, LBM_ERR_UNSUPPORTED, "no wall force for a multiphase instance");
   force[0] = force[1] = force[2] = 0.0;
   return LBM_OK;
 }

@@ -964,6 +964,33 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
   if (STATS) block_stats<BLOCK>(gmin, gmax, gsum, cnt, f64, b.stats + ti);
 }
 
+// Multiphase field helpers (Sec. III.B); the kernels follow the FP64 pass.
+template <int ST>
+struct MpField {
+  using T = float;
+};
+template <>
+struct MpField<LBM_F64> {
+  using T = double;
+};
+
+// Non-ideal pressure of Sec. III.B, Eq. eos.
+__device__ __forceinline__ double eos_p(double r) {
+  return r * (5.3e-2 +
+              r * (-3.818183621928911e-2 +
+                   r * (4.139745482116095e-3 +
+                        r * (3.748484095210317e-4 +
+                             r * (-1.4552652965531227e-4 + r * 1.2746947442749278e-5)))));
+}
+
+template <int ST>
+__device__ __forceinline__ void mp_put(const InstDev& I, uint32_t node, double rho) {
+  using FT = typename MpField<ST>::T;
+  FT* fld = static_cast<FT*>(I.mp_field);
+  fld[node] = (FT)rho;
+  fld[I.N + node] = (FT)sqrt(rho / 3.0 - eos_p(rho));
+}
+
 // ---------------------------------------------------------------------------
 // Boundary kernel: special nodes of the scanned regions.
 // ---------------------------------------------------------------------------
@@ -1051,7 +1078,7 @@ __global__ void __launch_bounds__(256) k_boundary_scan(const InstDev* __restrict
 // (Sec. II.C.1) and the KBC collision (Eqs. 1-6), both in FP64 whatever the
 // storage form, as for the other boundary nodes.  Consecutive list entries
 // are mostly consecutive nodes of a wall row, so the loads coalesce.
-template <int Q, int ST>
+template <int Q, int ST, bool PRE>
 __global__ void __launch_bounds__(64) k_boundary_wall(StepBuffers b, const uint2* __restrict__ list,
                                                      const uint32_t* __restrict__ count,
                                                      uint32_t cap, int stat0) {
@@ -1071,6 +1098,18 @@ __global__ void __launch_bounds__(64) k_boundary_wall(StepBuffers b, const uint2
     const Coord c = node_coord(I, e.y);
     double f[Q];
     gather_pre<Q, ST, double>(I, sb, fl, c.x, c.y, c.z, t1, f);
+    if constexpr (PRE) {
+      // Multiphase: the pre-collision state and its density, for the forced
+      // collision that follows.
+      double rt = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        db[i * I.stride + e.y] = S::enc_d(f[i]);
+        rt += f[i];
+      }
+      mp_put<ST>(I, e.y, 1.0 + rt);
+      continue;
+    }
     CollideParams<double> P;
     P.beta = I.beta;
     P.inv_beta = 1.0 / I.beta;
@@ -1160,7 +1199,7 @@ __device__ __forceinline__ int lag_slot(int i, int k) {
 // The arithmetic of the boundary nodes is FP64 for every storage form.
 // Workgroups (one wavefront) stride over the node list.
 // ---------------------------------------------------------------------------
-template <int Q, int ST>
+template <int Q, int ST, bool PRE>
 __global__ void __launch_bounds__(64) k_boundary_wave(StepBuffers b, const uint2* __restrict__ list,
                                                      const uint32_t* __restrict__ count,
                                                      uint32_t cap, int stat0) {
@@ -1379,6 +1418,14 @@ __global__ void __launch_bounds__(64) k_boundary_wave(StepBuffers b, const uint2
     }
     // Moments of the pre-collision state.
     const double rt = group_sum<GL>(pop ? d : 0.0);
+    if constexpr (PRE) {
+      // Multiphase: the pre-collision state and its density, for the forced
+      // collision that follows.
+      if (pop) db[i * stride + me] = S::enc_d(d);
+      if (active && lane == 0) mp_put<ST>(I, me, 1.0 + rt);
+      __syncthreads();
+      continue;
+    }
     const double jx = group_sum<GL>(pop ? cx(i) * d : 0.0);
     const double jy = group_sum<GL>(pop ? cy(i) * d : 0.0);
     const double jz = group_sum<GL>(pop ? cz<Q>(i) * d : 0.0);
@@ -1603,6 +1650,253 @@ __global__ void __launch_bounds__(256) k_neq_fixup(StepBuffers b, int stat0) {
   if (b.stats) block_stats<256>(gmin, gmax, gsum, cnt, f64, b.stats + stat0 + blockIdx.x);
 }
 
+
+// ---------------------------------------------------------------------------
+// Multiphase step (Sec. III.B).  After the boundary kernels have written the
+// pre-collision state of their nodes (their pre-collision mode), three
+// passes over the tiles:
+//   stage 0 (k_mp_stream): every node with no special flag pulls its
+//     populations into dst unchanged and writes its density and
+//     phi = sqrt(rho cs^2 - p(rho)) to the instance's fields;
+//   stage 1 (k_mp_lap): the lattice Laplacian of the density at every fluid
+//     node, lap X = (2/cs^2) sum_i W_i (X(x + c_i) - X(x));
+//   stage 2 (k_mp_collide): the body force
+//       F = 2 phi grad(phi) + kappa rho grad(lap rho) + kappa_w rho sum_i W_i s(x + c_i) c_i,
+//     with grad_a X = (1/cs^2) sum_i W_i c_ia X(x + c_i) (the kappa term's
+//     sign is the one the divergence of the Korteweg tensor gives; a
+//     neighbour that is not fluid gives the node's own value and s = 1),
+//     then the KBC collision in FP64 with the exact difference method: the
+//     post-collision state gains f^eq(rho, u + F/rho) - f^eq(rho, u), and
+//     gamma uses the scalar product weighted by 1 / f^eq(rho, u + F/rho).
+//     In place in dst.
+// Field element type: FP64 for FP64 storage, FP32 otherwise; an instance's
+// fields hold rho at [node], phi at [N + node] and lap at [2N + node].
+// An instance with multiphase off gets F = 0 (the plain KBC collision, in
+// FP64).
+// ---------------------------------------------------------------------------
+template <int Q, int ST>
+__global__ void __launch_bounds__(256) k_mp_stream(StepBuffers b, const Tile* __restrict__ tiles,
+                                                   int tile0) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  const Tile tl = tiles[tile0 + blockIdx.x];
+  const InstDev& I = b.insts[tl.inst];
+  if (!I.mp_field) return;
+  const T* __restrict__ sb = static_cast<const T*>(b.src) + I.pop_off;
+  T* __restrict__ db = static_cast<T*>(b.dst) + I.pop_off;
+  const uint8_t* fl = I.flag_off >= 0 ? b.flags + I.flag_off : nullptr;
+  const int nx = I.nx, ny = I.ny, nz = I.nz;
+  const uint32_t sy = (uint32_t)nx, sz = (uint32_t)nx * (uint32_t)ny;
+  const uint32_t wx = (uint32_t)(nx - 1), wy = (uint32_t)(ny - 1) * sy,
+                 wz = (uint32_t)(nz - 1) * sz;
+  for (int k = threadIdx.x; k < tl.count; k += 256) {
+    const uint32_t node = (uint32_t)(tl.node0 + k);
+    // Special nodes are the boundary kernels' (or solid); every source of
+    // any other node lies inside the instance, wrapping periodically.
+    if (fl && (fl[node] & FLAG_SPECIAL)) continue;
+    const Coord c = node_coord(I, node);
+    const uint32_t dm[3] = {c.x == 0 ? wx : 0u - 1u, c.y == 0 ? wy : 0u - sy,
+                            c.z == 0 ? wz : 0u - sz};
+    const uint32_t dp[3] = {c.x == nx - 1 ? 0u - wx : 1u, c.y == ny - 1 ? 0u - wy : sy,
+                            c.z == nz - 1 ? 0u - wz : sz};
+    auto dof = [&](int a, int ci) -> uint32_t { return ci == 0 ? 0u : (ci > 0 ? dm[a] : dp[a]); };
+    T v[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      // Source node index, formed modulo 2^32 (the -1 offsets are stored as
+      // their 32-bit complements) before it is widened.
+      const uint32_t src = node + dof(0, cx(i)) + dof(1, cy(i)) + (Q == 27 ? dof(2, cz<Q>(i)) : 0u);
+      v[i] = sb[i * I.stride + (int64_t)src];
+    }
+    double rt = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      db[i * I.stride + node] = v[i];
+      rt += (double)S::dec(v[i]);
+    }
+    mp_put<ST>(I, node, 1.0 + rt);
+  }
+}
+
+template <int Q, int ST>
+__global__ void __launch_bounds__(256) k_mp_lap(StepBuffers b, const Tile* __restrict__ tiles,
+                                                int tile0) {
+  using FT = typename MpField<ST>::T;
+  const Tile tl = tiles[tile0 + blockIdx.x];
+  const InstDev& I = b.insts[tl.inst];
+  if (!I.mp_field) return;
+  FT* fld = static_cast<FT*>(I.mp_field);
+  const uint8_t* fl = I.flag_off >= 0 ? b.flags + I.flag_off : nullptr;
+  for (int k = threadIdx.x; k < tl.count; k += 256) {
+    const uint32_t node = (uint32_t)(tl.node0 + k);
+    if (fl && (fl[node] & FLAG_SOLID)) continue;
+    const Coord c = node_coord(I, node);
+    const double r0 = (double)fld[node];
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      uint32_t m = node;
+      double v = r0;
+      if (resolve_nb(I, c.x, c.y, c.z, cx(i), cy(i), cz<Q>(i), m) &&
+          !(fl && (fl[m] & FLAG_SOLID)))
+        v = (double)fld[m];
+      s += weight<Q>(i) * (v - r0);
+    }
+    fld[2 * I.N + node] = (FT)(6.0 * s);
+  }
+}
+
+template <int Q>
+__device__ __forceinline__ double eq_dev_at(int i, double rt, double rho, const AxisEq<double>& ax,
+                                            const AxisEq<double>& ay, const AxisEq<double>& az) {
+  double E = pick3(cx(i), ax.e0, ax.ep, ax.em);
+  const double ey = pick3(cy(i), ay.e0, ay.ep, ay.em);
+  E = E + ey + E * ey;
+  if (Q == 27) {
+    const double ez = pick3(cz<Q>(i), az.e0, az.ep, az.em);
+    E = E + ez + E * ez;
+  }
+  return weight<Q>(i) * (rt + rho * E);
+}
+
+template <int Q, int ST>
+__global__ void __launch_bounds__(256) k_mp_collide(StepBuffers b, const Tile* __restrict__ tiles,
+                                                    int tile0) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  using FT = typename MpField<ST>::T;
+  constexpr int D = dims<Q>();
+  const int ti = tile0 + blockIdx.x;
+  const Tile tl = tiles[ti];
+  const InstDev& I = b.insts[tl.inst];
+  float gmin = 1e30f, gmax = -1e30f;
+  double gsum = 0.0;
+  uint32_t cnt = 0;
+  if (I.mp_field) {
+    T* __restrict__ db = static_cast<T*>(b.dst) + I.pop_off;
+    const FT* fld = static_cast<const FT*>(I.mp_field);
+    const uint8_t* fl = I.flag_off >= 0 ? b.flags + I.flag_off : nullptr;
+    const int64_t N = I.N, stride = I.stride;
+    const double beta = I.beta;
+    for (int k = threadIdx.x; k < tl.count; k += 256) {
+      const uint32_t node = (uint32_t)(tl.node0 + k);
+      if (fl && (fl[node] & FLAG_SOLID)) continue;
+      const Coord c = node_coord(I, node);
+      double d[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) d[i] = (double)S::dec(db[i * stride + node]);
+      double rt = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        rt += d[i];
+        j[0] += cx(i) * d[i];
+        j[1] += cy(i) * d[i];
+        j[2] += cz<Q>(i) * d[i];
+      }
+      const double rho = 1.0 + rt;
+      // ---- body force ------------------------------------------------------
+      double F[3] = {0.0, 0.0, 0.0};
+      if (I.mp) {
+        const double p0 = (double)fld[N + node], l0 = (double)fld[2 * N + node];
+        double gp[3] = {0.0, 0.0, 0.0}, gl[3] = {0.0, 0.0, 0.0}, wt[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          if (i == rest<Q>()) continue;
+          uint32_t m = node;
+          const bool f = resolve_nb(I, c.x, c.y, c.z, cx(i), cy(i), cz<Q>(i), m) &&
+                         !(fl && (fl[m] & FLAG_SOLID));
+          const double vp = f ? (double)fld[N + m] : p0;
+          const double vl = f ? (double)fld[2 * N + m] : l0;
+          const double w = weight<Q>(i);
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            const int ca = comp<Q>(i, a);
+            if (ca == 0) continue;
+            gp[a] += w * ca * vp;
+            gl[a] += w * ca * vl;
+            if (!f) wt[a] += w * ca;
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+          F[a] = 2.0 * p0 * (3.0 * gp[a]) + I.mp_kappa * rho * (3.0 * gl[a]) +
+                 I.mp_kappa_w * rho * wt[a];
+      }
+      // ---- forced collision (FP64) -------------------------------------------
+      const double ir = 1.0 / rho;
+      const double u[3] = {j[0] * ir, j[1] * ir, j[2] * ir};
+      const double us[3] = {u[0] + F[0] * ir, u[1] + F[1] * ir, u[2] + F[2] * ir};
+      bool ok = rho > 0.0 && isfinite(rho);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        ok = ok && fabs(u[a]) < 1.0 && fabs(us[a]) < 1.0 && isfinite(us[a]);
+      if (!ok) {
+        atomicOr(b.err, 1u);
+        continue;
+      }
+      const AxisEq<double> ax = axis_eq(u[0]), ay = axis_eq(u[1]);
+      const AxisEq<double> az = Q == 27 ? axis_eq(u[2]) : ay;
+      const AxisEq<double> sx = axis_eq(us[0]), sy = axis_eq(us[1]);
+      const AxisEq<double> sz = Q == 27 ? axis_eq(us[2]) : sy;
+      // Second moments of Delta = f - f^eq(rho, u).
+      double Pxx = 0.0, Pyy = 0.0, Pzz = 0.0, Pxy = 0.0, Pxz = 0.0, Pyz = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const double dl = d[i] - eq_dev_at<Q>(i, rt, rho, ax, ay, az);
+        if (cx(i)) Pxx += dl;
+        if (cy(i)) Pyy += dl;
+        if (cz<Q>(i)) Pzz += dl;
+        Pxy += (double)(cx(i) * cy(i)) * dl;
+        Pxz += (double)(cx(i) * cz<Q>(i)) * dl;
+        Pyz += (double)(cy(i) * cz<Q>(i)) * dl;
+      }
+      double Tr, Dxx, Dyy, Dzz;
+      if (Q == 27) {
+        Tr = Pxx + Pyy + Pzz;
+        Dxx = Pxx - Tr / 3.0;
+        Dyy = Pyy - Tr / 3.0;
+        Dzz = -(Dxx + Dyy);
+      } else {
+        Tr = Pxx + Pyy;
+        Dxx = 0.5 * (Pxx - Pyy);
+        Dyy = -Dxx;
+        Dzz = 0.0;
+      }
+      const double ts = I.trace_in_s ? Tr : 0.0;
+      auto s_of = [&](int i) -> double {
+        const int c0 = cx(i), c1 = cy(i), c2 = cz<Q>(i);
+        const int nzc = (c0 != 0) + (c1 != 0) + (c2 != 0);
+        if (nzc == 1) return 0.5 * (c0 != 0 ? Dxx : (c1 != 0 ? Dyy : Dzz)) + ts * (0.5 / D);
+        if (nzc == 2) return 0.25 * (c0 * c1 * Pxy + c0 * c2 * Pxz + c1 * c2 * Pyz);
+        if (nzc == 0) return -ts;
+        return 0.0;
+      };
+      double aa = 0.0, bb = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const double dl = d[i] - eq_dev_at<Q>(i, rt, rho, ax, ay, az);
+        const double si = s_of(i), hi = dl - si;
+        const double inv = 1.0 / (weight<Q>(i) + eq_dev_at<Q>(i, rt, rho, sx, sy, sz));
+        aa += si * hi * inv;
+        bb += hi * hi * inv;
+      }
+      double gamma = 2.0;
+      if (!I.collision && bb != 0.0) gamma = 1.0 / beta - (2.0 - 1.0 / beta) * aa / bb;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const double fe = eq_dev_at<Q>(i, rt, rho, ax, ay, az);
+        const double fs = eq_dev_at<Q>(i, rt, rho, sx, sy, sz);
+        const double si = s_of(i), hi = (d[i] - fe) - si;
+        db[i * stride + node] = S::enc_d(d[i] - beta * (2.0 * si + gamma * hi) + (fs - fe));
+      }
+      gmin = fminf(gmin, (float)gamma);
+      gmax = fmaxf(gmax, (float)gamma);
+      gsum += gamma;
+      cnt += 1;
+    }
+  }
+  if (b.stats) block_stats<256>(gmin, gmax, gsum, cnt, cnt, b.stats + ti);
+}
 
 // ---------------------------------------------------------------------------
 // Initialisation, checkpoint encode/decode, moments.
@@ -2006,16 +2300,39 @@ template <int Q, int ST>
 static hipError_t launch_boundary(const StepBuffers& b, const Region* regions,
                                   const BoxTile* btiles, int bt0, int nbt, uint2* list,
                                   uint32_t cap, uint32_t* count, int nwg, int nwall, int stat0,
-                                  hipStream_t s) {
+                                  bool pre, hipStream_t s) {
   if (nbt <= 0 || (nwg <= 0 && nwall <= 0)) return hipSuccess;
   hipLaunchKernelGGL((k_boundary_scan<Q>), dim3(nbt), dim3(256), 0, s, b.insts, regions, btiles,
                      bt0, b.flags, list, cap, count);
-  if (nwg > 0)
-    hipLaunchKernelGGL((k_boundary_wave<Q, ST>), dim3(nwg), dim3(64), 0, s, b, list, count, cap,
-                       stat0);
-  if (nwall > 0)
-    hipLaunchKernelGGL((k_boundary_wall<Q, ST>), dim3(nwall), dim3(64), 0, s, b, list + cap,
-                       count + 1, cap, stat0 + nwg);
+  if (nwg > 0) {
+    if (pre)
+      hipLaunchKernelGGL((k_boundary_wave<Q, ST, true>), dim3(nwg), dim3(64), 0, s, b, list,
+                         count, cap, stat0);
+    else
+      hipLaunchKernelGGL((k_boundary_wave<Q, ST, false>), dim3(nwg), dim3(64), 0, s, b, list,
+                         count, cap, stat0);
+  }
+  if (nwall > 0) {
+    if (pre)
+      hipLaunchKernelGGL((k_boundary_wall<Q, ST, true>), dim3(nwall), dim3(64), 0, s, b,
+                         list + cap, count + 1, cap, stat0 + nwg);
+    else
+      hipLaunchKernelGGL((k_boundary_wall<Q, ST, false>), dim3(nwall), dim3(64), 0, s, b,
+                         list + cap, count + 1, cap, stat0 + nwg);
+  }
+  return hipGetLastError();
+}
+
+template <int Q, int ST>
+static hipError_t launch_mp(int stage, const StepBuffers& b, const Tile* tiles, int tile0,
+                            int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (stage == 0)
+    hipLaunchKernelGGL((k_mp_stream<Q, ST>), dim3(ntiles), dim3(256), 0, s, b, tiles, tile0);
+  else if (stage == 1)
+    hipLaunchKernelGGL((k_mp_lap<Q, ST>), dim3(ntiles), dim3(256), 0, s, b, tiles, tile0);
+  else
+    hipLaunchKernelGGL((k_mp_collide<Q, ST>), dim3(ntiles), dim3(256), 0, s, b, tiles, tile0);
   return hipGetLastError();
 }
 
@@ -2106,7 +2423,7 @@ static const Ops* ops_for() {
   static const Ops o = {launch_bulk<Q, ST>,    launch_boundary<Q, ST>, launch_geometry<Q, ST>,
                         launch_init<Q, ST>,    launch_decode<Q, ST>,   launch_encode<Q, ST>,
                         launch_moments<Q, ST>, launch_fixup<Q, ST>,    launch_force<Q, ST>,
-                        launch_decode_box<Q, ST>};
+                        launch_decode_box<Q, ST>, launch_mp<Q, ST>};
   return &o;
 }
 

@@ -60,7 +60,7 @@ struct Ops {
   // clears them).  Statistics go to stats[stat0, stat0 + nwg + nwall).
   hipError_t (*boundary)(const StepBuffers& b, const Region* regions, const BoxTile* btiles,
                          int bt0, int nbt, uint2* list, uint32_t cap, uint32_t* count, int nwg,
-                         int nwall, int stat0, hipStream_t s);
+                         int nwall, int stat0, bool pre, hipStream_t s);
   // Geometry update over the swept boxes at time clock + toff: stage 0 marks
   // SOLID_NEXT and refills the fresh nodes of src, stage 1 does nothing (kept
   // for the call sequence), stage 2 makes SOLID_NEXT current and marks the
@@ -95,6 +95,15 @@ struct Ops {
   // Full populations of the box [lo, lo + ext) (x-fastest, population-major).
   hipError_t (*decode_box)(const InstDev* insts, int inst, const int* lo, const int* ext,
                            const void* buf, double* f, hipStream_t s);
+  // Multiphase step passes over tiles (Sec. III.B): stage 0 streams the nodes
+  // with no special flag into dst and fills the density and phi fields,
+  // stage 1 the density Laplacian, stage 2 forms the body force and the
+  // forced collision of every fluid node in place.  Run after the boundary
+  // launch in its pre-collision mode (pre = true: the boundary kernels write
+  // the pre-collision state and density of their nodes instead of
+  // colliding).
+  hipError_t (*mp)(int stage, const StepBuffers& b, const Tile* tiles, int tile0, int ntiles,
+                   hipStream_t s);
 };
 
 const Ops* get_ops(int Q, int storage);

@@ -203,6 +203,13 @@ struct InstDev {
   double bin_lo[3];
   double bin_h;
   int bin_n[3];
+  // Multiphase forcing (Sec. III.B): on (1) or off, surface-tension and
+  // wetting coefficients, and the instance's density, phi and Laplacian
+  // fields (N values each; FP64 for FP64 storage, FP32 otherwise), or null
+  // when the context steps without the multiphase pipeline.
+  int mp;
+  double mp_kappa, mp_kappa_w;
+  void* mp_field;
 };
 
 // A contiguous run of nodes of one instance, processed by one workgroup.

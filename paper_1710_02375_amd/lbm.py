@@ -100,6 +100,7 @@ def lib():
         L.lbm_set_populations.argtypes = [vp, C.c_int, _dp]
         L.lbm_get_populations_box.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                               _dp]
+        L.lbm_set_multiphase.argtypes = [vp, C.c_int, C.c_int, C.c_double, C.c_double]
         L.lbm_set_stats.argtypes = [vp, C.c_int]
         L.lbm_set_launch_mode.argtypes = [vp, C.c_int]
         L.lbm_autotune.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int)]
@@ -120,7 +121,7 @@ def lib():
 
 EXPORTED = ["lbm_create", "lbm_destroy", "lbm_init_fields", "lbm_set_geometry", "lbm_step",
             "lbm_moments", "lbm_wall_force", "lbm_wall_force_noalloc", "lbm_get_populations",
-            "lbm_set_populations", "lbm_get_populations_box",
+            "lbm_set_populations", "lbm_get_populations_box", "lbm_set_multiphase",
             "lbm_set_stats", "lbm_set_launch_mode", "lbm_autotune", "lbm_set_variant",
             "lbm_variant_count", "lbm_variant_name", "lbm_info", "lbm_synchronize",
             "lbm_status_string", "lbm_last_error"]
@@ -316,6 +317,12 @@ def lbm_set_populations(ctx, inst, f):
     return _check(ctx, lib().lbm_set_populations(ctx, int(inst), _f64(f)))
 
 
+def lbm_set_multiphase(ctx, inst, kappa, kappa_w=0.0, enable=True):
+    """Multiphase forcing of Sec. III.B on instance inst (or off)."""
+    return _check(ctx, lib().lbm_set_multiphase(ctx, int(inst), int(bool(enable)), float(kappa),
+                                                float(kappa_w)))
+
+
 def lbm_set_stats(ctx, enabled):
     return _check(ctx, lib().lbm_set_stats(ctx, int(bool(enabled))))
 
@@ -390,6 +397,9 @@ class Solver:
 
     def set_body(self, kind, params=(), inst=0, verts=None, vert_vel=None, tris=None):
         lbm_set_geometry(self.ctx, inst, kind, params, verts, vert_vel, tris)
+
+    def set_multiphase(self, kappa, kappa_w=0.0, inst=0, enable=True):
+        lbm_set_multiphase(self.ctx, inst, kappa, kappa_w, enable)
 
     def step(self, n=1):
         lbm_step(self.ctx, n)
