@@ -294,6 +294,57 @@ def sphere_workload(lbm, torch, args, forms=("f64", "f32", "f16")):
             "forms": out}
 
 
+def multiphase_form(lbm, torch, storage, steps, warmup, dims=(320, 250, 320), kappa=0.025,
+                    kappa_w=-0.145, nu=0.05):
+    """Droplet of diameter 80 hitting a non-wetting wall (Sec. III.B
+    multiphase KBC, D3Q27): MLUPS and the step's achieved bandwidth over the
+    bytes the three multiphase passes move per node."""
+    import workloads as W
+
+    nx, ny, nz = dims
+    rho, u, info = W.droplet_impact(nx, ny, nz)
+    stream = torch.cuda.Stream()
+    s = lbm.Solver([dict(Q=27, nx=nx, ny=ny, nz=nz, nu=nu, storage=storage,
+                         faces=info["faces"])], stream=stream)
+    s.set_multiphase(kappa, kappa_w)
+    s.init_fields(rho, u)
+    s.step(warmup)
+    stream.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    s.step(steps)
+    ev1.record(stream)
+    stream.synchronize()
+    t1 = time.perf_counter()
+    r, uu, tot = s.moments()
+    s.close()
+    N = nx * ny * nz
+    ms = (t1 - t0) * 1e3 / steps
+    kms = ev0.elapsed_time(ev1) / steps
+    es = 8 if storage == "f64" else 4
+    # Populations read and written twice (stream pass, collision pass), the
+    # density and phi fields written once and read once, the Laplacian
+    # field written and read once.
+    moved = 4 * 27 * es + 6 * es
+    return {"MLUPS": round(N / (ms * 1e3), 1), "ms_per_step": round(ms, 5),
+            "event_ms_per_step": round(kms, 5), "bytes_per_lattice_update": moved,
+            "achieved_GBs": round(moved * N / (kms * 1e-3) / 1e9, 1),
+            "frac_of_hbm_peak": round(moved * N / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "rho_max": round(float(r.max()), 4), "rho_min": round(float(r[r > 0].min()), 5),
+            "mass": tot["mass"], "gamma_mean": tot.get("gamma_mean")}
+
+
+def multiphase_workload(lbm, torch, args):
+    out = {storage: multiphase_form(lbm, torch, storage, args.mp_steps, 20)
+           for storage in ("f32", "f64")}
+    return {"metric": "MLUPS, multiphase KBC", "unit": "MLUPS",
+            "config": {"workload": "D3Q27 multiphase KBC droplet impact, 320x250x320, droplet "
+                                   "diameter 80, kappa 0.025, kappa_w -0.145 (non-wetting), "
+                                   "walls at -y/+y, %d steps" % args.mp_steps},
+            "forms": out}
+
+
 def tg512_workload(lbm, torch, args):
     """Config: D3Q27 TG 512^3, Re=1600: MLUPS and HBM fraction per storage form,
     velocity error of each against the FP64 form at steps 100 and 1000."""
@@ -419,7 +470,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--variant", default=None, help="bulk-kernel variant (default: autotune)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64"])
-    ap.add_argument("--workload", default="tg256", choices=["tg256", "tg512", "sphere", "batched"],
+    ap.add_argument("--mp-steps", type=int, default=200)
+    ap.add_argument("--workload", default="tg256",
+                    choices=["tg256", "tg512", "sphere", "batched", "multiphase"],
                     help="tg256 is the headline line; the others print their own line")
     ap.add_argument("--sphere-steps", type=int, default=1200)
     ap.add_argument("--sphere-sample", type=int, default=200)
@@ -449,6 +502,9 @@ def main():
                           "unit": "MLUPS", "config": {"workload": "64 D2Q9 KBC flap channels "
                                                       "(seed 2375), FP32"}, "forms": r}),
               flush=True)
+        return
+    if args.workload == "multiphase":
+        print(json.dumps(multiphase_workload(lbm, torch, args)), flush=True)
         return
     if args.workload == "tg512":
         print(json.dumps(tg512_workload(lbm, torch, args)), flush=True)

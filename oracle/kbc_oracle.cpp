@@ -1025,6 +1025,24 @@ void step_once(Domain& d) {
       grad_fstar(L, rho_t, ut, Pi, fs);
       for (int i = 0; i < Q; ++i)
         if (missing[i]) f[i] = fs[i];
+      // Multiphase: the filled populations are scaled so that they carry the
+      // mass that bounce-back would return, rho_t less the known
+      // populations (the node then holds the target density exactly).  The
+      // paper gives no form of Grad's fill for the multiphase model; the
+      // unscaled fill lets the non-equilibrium of the wetting force at wall
+      // nodes add mass every step.
+      if (d.mp) {
+        double sk = 0.0, sm = 0.0;
+        for (int i = 0; i < Q; ++i) {
+          if (missing[i]) sm += f[i];
+          else sk += f[i];
+        }
+        if (sm > 0.0) {
+          const double lam = (rho_t - sk) / sm;
+          for (int i = 0; i < Q; ++i)
+            if (missing[i]) f[i] *= lam;
+        }
+      }
     }
     // 5. Inflow node: all populations at equilibrium with the inflow velocity
     //    and the lagged density of the interior neighbour x + e_x (so the

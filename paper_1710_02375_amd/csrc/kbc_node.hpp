@@ -537,6 +537,161 @@ __device__ __forceinline__ bool collide(R (&d)[Q], const CollideParams<R>& P, Co
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// Forced KBC collision in FP64 (Sec. III.B): body force F enters by the exact
+// difference method and the stabiliser uses the shifted scalar product,
+//   f' = f - beta (2 Delta s + gamma Delta h) + f^eq(rho, u + du) - f^eq(rho, u),
+//   gamma = 1/beta - (2 - 1/beta) <Ds|Dh>_s / <Dh|Dh>_s,
+//   <X|Y>_s = sum X_i Y_i / f^eq_i(rho, u + du),  du = F / rho,
+// with Delta s and Delta h about f^eq(rho, u).  Written as
+//   f' - W = (f^eq(rho, u + du) - W) + Delta - beta (2 Delta s + gamma Delta h).
+// The state stays in its storage type V (the deviations f - W as stored, so
+// FP32 storage keeps 27 single registers); every quantity is formed in FP64,
+// Delta_i = d_i - (f^eq_i - W_i) again in each pass from the tensor-product
+// factors of the equilibria.  The result is written back into d, rounded to
+// V.  FP64 leaves no mass or momentum in Delta worth projecting.
+// Returns false (state left unchanged) if rho <= 0, |u_a| >= 1,
+// |u_a + du_a| >= 1 or the state is not finite.
+// ---------------------------------------------------------------------------
+template <int Q, typename V>
+__device__ __forceinline__ bool collide_forced(V* p, int64_t stride, const double (&F)[3],
+                                               double beta, int lbgk, int trace_in_s,
+                                               float& gamma_out) {
+  using R = double;
+  constexpr int D = dims<Q>();
+  // Population i of the node; read again in every pass (from cache), the
+  // memory clobbers between passes keep the compiler from holding them all.
+  auto ld = [&](int i) -> R { return (R)p[i * stride]; };
+  R rt = R(0), j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R v = ld(i);
+    rt += v;
+    if (cx(i)) j[0] += R(cx(i)) * v;
+    if (cy(i)) j[1] += R(cy(i)) * v;
+    if (cz<Q>(i)) j[2] += R(cz<Q>(i)) * v;
+  }
+  const R rho = R(1) + rt;
+  const R ir = R(1) / rho;
+  const R u[3] = {j[0] * ir, j[1] * ir, j[2] * ir};
+  const R us[3] = {u[0] + F[0] * ir, u[1] + F[1] * ir, u[2] + F[2] * ir};
+  bool ok = rho > R(0) && isfinite(rho);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ok = ok && fabs(u[a]) < R(1) && fabs(us[a]) < R(1) && isfinite(us[a]);
+  if (!ok) {
+    gamma_out = 2.0f;
+    return false;
+  }
+  const R wv[3] = {R(1.0 / 6.0), R(2.0 / 3.0), R(1.0 / 6.0)};
+  // Per-axis factors at (rho, v) (rho folded into x): dxr = rho p_x - w,
+  // py = p_y, dy = p_y - w, dz = p_z - w; f^eq_i - W_i from them.
+  struct Fac {
+    R dxr[3], py[3], dy[3], dz[3];
+    R g[3][3];   // 1 / (w (1 + e)) per axis and c, x row times 1/rho
+  };
+  auto factors = [&](const R (&v)[3], Fac& f) {
+    AxisEq<R> A[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) A[a] = axis_eq(v[a]);
+    if (D == 2) A[2] = A[1];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      f.g[a][0] = A[a].gm;
+      f.g[a][1] = A[a].g0;
+      f.g[a][2] = A[a].gp;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f.g[0][k] *= ir;
+    const R ex[3] = {A[0].em, A[0].e0, A[0].ep};
+    const R ey[3] = {A[1].em, A[1].e0, A[1].ep};
+    const R ez[3] = {A[2].em, A[2].e0, A[2].ep};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      f.dxr[k] = wv[k] * (rt + rho * ex[k]);
+      f.dy[k] = wv[k] * ey[k];
+      f.py[k] = wv[k] + f.dy[k];
+      f.dz[k] = wv[k] * ez[k];
+    }
+  };
+  auto eqdev = [&](int i, const Fac& f) -> R {
+    const int a = i % 3, b = (i / 3) % 3, c = i / 9;
+    const R dxy = f.dxr[a] * f.py[b] + wv[a] * f.dy[b];   // rho p_x p_y - w_a w_b
+    if (Q == 27) return wv[c] * dxy + (dxy + R(w1d(a - 1) * w1d(b - 1))) * f.dz[c];
+    return dxy;
+  };
+  Fac fu, fs;
+  factors(u, fu);
+  factors(us, fs);
+  // Second moments of Delta.
+  R Pxx = R(0), Pyy = R(0), Pzz = R(0), Pxy = R(0), Pxz = R(0), Pyz = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R dl = ld(i) - eqdev(i, fu);
+    if (cx(i)) Pxx += dl;
+    if (cy(i)) Pyy += dl;
+    if (cz<Q>(i)) Pzz += dl;
+    if (cx(i) * cy(i)) Pxy += R(cx(i) * cy(i)) * dl;
+    if (cx(i) * cz<Q>(i)) Pxz += R(cx(i) * cz<Q>(i)) * dl;
+    if (cy(i) * cz<Q>(i)) Pyz += R(cy(i) * cz<Q>(i)) * dl;
+  }
+  R T, Dxx, Dyy, Dzz;
+  if (Q == 27) {
+    T = Pxx + Pyy + Pzz;
+    const R t3 = T * R(1.0 / 3.0);
+    Dxx = Pxx - t3;
+    Dyy = Pyy - t3;
+    Dzz = -(Dxx + Dyy);
+  } else {
+    T = Pxx + Pyy;
+    Dxx = R(0.5) * (Pxx - Pyy);
+    Dyy = -Dxx;
+    Dzz = R(0);
+  }
+  const R ts = trace_in_s ? T : R(0);
+  const R tf = ts * R(0.5 / D);
+  const R Fx = R(0.5) * Dxx + tf, Fy = R(0.5) * Dyy + tf, Fz = R(0.5) * Dzz + tf;
+  const R Exy = R(0.25) * Pxy, Exz = R(0.25) * Pxz, Eyz = R(0.25) * Pyz;
+  auto ds_of = [&](int i) -> R {
+    const int n = nnz<Q>(i);
+    if (n == 1) return cx(i) != 0 ? Fx : (cy(i) != 0 ? Fy : Fz);
+    if (n == 2) {
+      const R e = (cx(i) != 0 && cy(i) != 0) ? Exy : (cx(i) != 0 ? Exz : Eyz);
+      const int sg = cx(i) * cy(i) + cx(i) * cz<Q>(i) + cy(i) * cz<Q>(i);
+      return sg > 0 ? e : -e;
+    }
+    if (n == 0) return -ts;
+    return R(0);
+  };
+  R gamma = R(2);
+  if (!lbgk) {
+    asm volatile("" ::: "memory");
+    // 1/f^eq_i(rho, u + du) = g_x(a) g_y(b) g_z(c).
+    R a = R(0), b = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R si = ds_of(i);
+      const R hi = (ld(i) - eqdev(i, fu)) - si;
+      R g = fs.g[0][i % 3] * fs.g[1][(i / 3) % 3];
+      if (Q == 27) g *= fs.g[2][i / 9];
+      const R hg = hi * g;
+      b += hg * hi;
+      a += hg * si;
+    }
+    if (b != R(0)) gamma = R(1) / beta - (R(2) - R(1) / beta) * a / b;
+  }
+  const R bg = beta * gamma, b2 = R(2) * beta;
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R si = ds_of(i);
+    const R dl = ld(i) - eqdev(i, fu);
+    const R hi = dl - si;
+    p[i * stride] = (V)(eqdev(i, fs) + dl - bg * hi - b2 * si);
+  }
+  gamma_out = (float)gamma;
+  return true;
+}
+
 // Grad's approximation (Sec. II.C.1) as a deviation from W_i, cs^2 = 1/3:
 //   f*_i - W_i = W_i [ rho - 1 + 3 rho c.v + (9/2)(Pi - rho/3 I):(c c - I/3) ].
 // Pi is given as (xx, yy, zz, xy, xz, yz).

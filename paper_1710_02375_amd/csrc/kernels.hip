@@ -653,6 +653,22 @@ __device__ void gather_pre(const InstDev& I, const typename Store<ST>::T* sb, co
 #pragma unroll
   for (int i = 0; i < Q; ++i)
     if ((miss >> i) & 1u) f[i] = grad_dev<Q, R>(i, rho_t, ut, Pi);
+  if (I.mp) {
+    // Multiphase: the filled populations carry the mass that bounce-back
+    // would return, rho_t less the known populations (scaled as full f).
+    R sk = R(0), sm = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if ((miss >> i) & 1u) sm += f[i] + R(weight<Q>(i));
+      else sk += f[i] + R(weight<Q>(i));
+    }
+    if (sm > R(0)) {
+      const R lam = (rho_t - sk) / sm;
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        if ((miss >> i) & 1u) f[i] = lam * (f[i] + R(weight<Q>(i))) - R(weight<Q>(i));
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1416,6 +1432,16 @@ __global__ void __launch_bounds__(64) k_boundary_wave(StepBuffers b, const uint2
         d = grad_dev<Q, double>(i, rho_t, ut, Pi);
       }
     }
+    {
+      // Multiphase: the filled populations carry the mass that bounce-back
+      // would return, rho_t less the known populations (scaled as full f).
+      // The sums run on every wavefront so that the lane exchanges stay
+      // uniform; only multiphase instances apply them.
+      const double fi = pop ? d + weight<Q>(i) : 0.0;
+      const double sm = group_sum<GL>(pop && mi ? fi : 0.0);
+      const double sk = group_sum<GL>(pop && !mi ? fi : 0.0);
+      if (I.mp && pop && mi && sm > 0.0) d = (rho_t - sk) / sm * fi - weight<Q>(i);
+    }
     // Moments of the pre-collision state.
     const double rt = group_sum<GL>(pop ? d : 0.0);
     if constexpr (PRE) {
@@ -1727,40 +1753,39 @@ __global__ void __launch_bounds__(256) k_mp_lap(StepBuffers b, const Tile* __res
   if (!I.mp_field) return;
   FT* fld = static_cast<FT*>(I.mp_field);
   const uint8_t* fl = I.flag_off >= 0 ? b.flags + I.flag_off : nullptr;
+  const int nx = I.nx, ny = I.ny, nz = I.nz;
+  const uint32_t sy = (uint32_t)nx, sz = (uint32_t)nx * (uint32_t)ny;
+  const uint32_t wx = (uint32_t)(nx - 1), wy = (uint32_t)(ny - 1) * sy,
+                 wz = (uint32_t)(nz - 1) * sz;
   for (int k = threadIdx.x; k < tl.count; k += 256) {
     const uint32_t node = (uint32_t)(tl.node0 + k);
-    if (fl && (fl[node] & FLAG_SOLID)) continue;
+    const uint8_t fv = fl ? fl[node] : 0;
+    if (fv & FLAG_SOLID) continue;
     const Coord c = node_coord(I, node);
+    // Neighbours as in the collision pass: wrap offsets for nodes with no
+    // face or body flag, resolved and flag-tested otherwise.
+    const bool edge = fv & (FLAG_STATIC | FLAG_BODY);
+    const uint32_t dn[3] = {c.x == 0 ? wx : 0u - 1u, c.y == 0 ? wy : 0u - sy,
+                            c.z == 0 ? wz : 0u - sz};
+    const uint32_t up[3] = {c.x == nx - 1 ? 0u - wx : 1u, c.y == ny - 1 ? 0u - wy : sy,
+                            c.z == nz - 1 ? 0u - wz : sz};
+    auto off = [&](int a, int ci) -> uint32_t { return ci == 0 ? 0u : (ci > 0 ? up[a] : dn[a]); };
     const double r0 = (double)fld[node];
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      uint32_t m = node;
-      double v = r0;
-      if (resolve_nb(I, c.x, c.y, c.z, cx(i), cy(i), cz<Q>(i), m) &&
-          !(fl && (fl[m] & FLAG_SOLID)))
-        v = (double)fld[m];
-      s += weight<Q>(i) * (v - r0);
+      uint32_t m = node + off(0, cx(i)) + off(1, cy(i)) + (Q == 27 ? off(2, cz<Q>(i)) : 0u);
+      if (edge && !(resolve_nb(I, c.x, c.y, c.z, cx(i), cy(i), cz<Q>(i), m) &&
+                    !(fl[m] & FLAG_SOLID)))
+        m = node;
+      s += weight<Q>(i) * ((double)fld[m] - r0);
     }
     fld[2 * I.N + node] = (FT)(6.0 * s);
   }
 }
 
-template <int Q>
-__device__ __forceinline__ double eq_dev_at(int i, double rt, double rho, const AxisEq<double>& ax,
-                                            const AxisEq<double>& ay, const AxisEq<double>& az) {
-  double E = pick3(cx(i), ax.e0, ax.ep, ax.em);
-  const double ey = pick3(cy(i), ay.e0, ay.ep, ay.em);
-  E = E + ey + E * ey;
-  if (Q == 27) {
-    const double ez = pick3(cz<Q>(i), az.e0, az.ep, az.em);
-    E = E + ez + E * ez;
-  }
-  return weight<Q>(i) * (rt + rho * E);
-}
-
 template <int Q, int ST>
-__global__ void __launch_bounds__(256) k_mp_collide(StepBuffers b, const Tile* __restrict__ tiles,
+__global__ void __launch_bounds__(256, 2) k_mp_collide(StepBuffers b, const Tile* __restrict__ tiles,
                                                     int tile0) {
   using S = Store<ST>;
   using T = typename S::T;
@@ -1774,124 +1799,86 @@ __global__ void __launch_bounds__(256) k_mp_collide(StepBuffers b, const Tile* _
   uint32_t cnt = 0;
   if (I.mp_field) {
     T* __restrict__ db = static_cast<T*>(b.dst) + I.pop_off;
-    const FT* fld = static_cast<const FT*>(I.mp_field);
+    const FT* __restrict__ fld = static_cast<const FT*>(I.mp_field);
     const uint8_t* fl = I.flag_off >= 0 ? b.flags + I.flag_off : nullptr;
     const int64_t N = I.N, stride = I.stride;
-    const double beta = I.beta;
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
+    const uint32_t sy = (uint32_t)nx, sz = (uint32_t)nx * (uint32_t)ny;
+    const uint32_t wx = (uint32_t)(nx - 1), wy = (uint32_t)(ny - 1) * sy,
+                   wz = (uint32_t)(nz - 1) * sz;
     for (int k = threadIdx.x; k < tl.count; k += 256) {
       const uint32_t node = (uint32_t)(tl.node0 + k);
-      if (fl && (fl[node] & FLAG_SOLID)) continue;
+      const uint8_t fv = fl ? fl[node] : 0;
+      if (fv & FLAG_SOLID) continue;
       const Coord c = node_coord(I, node);
-      double d[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) d[i] = (double)S::dec(db[i * stride + node]);
-      double rt = 0.0, j[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        rt += d[i];
-        j[0] += cx(i) * d[i];
-        j[1] += cy(i) * d[i];
-        j[2] += cz<Q>(i) * d[i];
-      }
-      const double rho = 1.0 + rt;
-      // ---- body force ------------------------------------------------------
+      // ---- body force, before the populations are loaded -------------------
       double F[3] = {0.0, 0.0, 0.0};
       if (I.mp) {
-        const double p0 = (double)fld[N + node], l0 = (double)fld[2 * N + node];
+        // A node with no face or body flag has only fluid neighbours, inside
+        // the instance or across periodic faces (32-bit wrap offsets as in
+        // the stream pass); the others resolve each neighbour and read its
+        // flag.  A neighbour that is not fluid reads the node's own values.
+        const bool edge = fv & (FLAG_STATIC | FLAG_BODY);
+        const uint32_t dn[3] = {c.x == 0 ? wx : 0u - 1u, c.y == 0 ? wy : 0u - sy,
+                                c.z == 0 ? wz : 0u - sz};
+        const uint32_t up[3] = {c.x == nx - 1 ? 0u - wx : 1u, c.y == ny - 1 ? 0u - wy : sy,
+                                c.z == nz - 1 ? 0u - wz : sz};
+        auto off = [&](int a, int ci) -> uint32_t { return ci == 0 ? 0u : (ci > 0 ? up[a] : dn[a]); };
+        const double rho0 = (double)fld[node];
+        const double p0 = (double)fld[N + node];
         double gp[3] = {0.0, 0.0, 0.0}, gl[3] = {0.0, 0.0, 0.0}, wt[3] = {0.0, 0.0, 0.0};
+        if (!edge) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          if (i == rest<Q>()) continue;
-          uint32_t m = node;
-          const bool f = resolve_nb(I, c.x, c.y, c.z, cx(i), cy(i), cz<Q>(i), m) &&
-                         !(fl && (fl[m] & FLAG_SOLID));
-          const double vp = f ? (double)fld[N + m] : p0;
-          const double vl = f ? (double)fld[2 * N + m] : l0;
-          const double w = weight<Q>(i);
+          for (int i = 0; i < Q; ++i) {
+            if (i == rest<Q>()) continue;
+            const uint32_t m =
+                node + off(0, cx(i)) + off(1, cy(i)) + (Q == 27 ? off(2, cz<Q>(i)) : 0u);
+            const double vp = (double)fld[N + m];
+            const double vl = (double)fld[2 * N + m];
+            const double w = weight<Q>(i);
 #pragma unroll
-          for (int a = 0; a < D; ++a) {
-            const int ca = comp<Q>(i, a);
-            if (ca == 0) continue;
-            gp[a] += w * ca * vp;
-            gl[a] += w * ca * vl;
-            if (!f) wt[a] += w * ca;
+            for (int a = 0; a < D; ++a) {
+              const int ca = comp<Q>(i, a);
+              if (ca == 0) continue;
+              gp[a] += w * ca * vp;
+              gl[a] += w * ca * vl;
+            }
+          }
+        } else {
+#pragma unroll 1
+          for (int i = 0; i < Q; ++i) {
+            const int c0 = i % 3 - 1, c1 = (i / 3) % 3 - 1, c2 = Q == 27 ? i / 9 - 1 : 0;
+            if (c0 == 0 && c1 == 0 && c2 == 0) continue;
+            uint32_t m = node;
+            const bool f = resolve_nb(I, c.x, c.y, c.z, c0, c1, c2, m) && !(fl[m] & FLAG_SOLID);
+            if (!f) m = node;
+            const double vp = (double)fld[N + m];
+            const double vl = (double)fld[2 * N + m];
+            const double w = w1d(c0) * w1d(c1) * (Q == 27 ? w1d(c2) : 1.0);
+            const int cc[3] = {c0, c1, c2};
+            for (int a = 0; a < D; ++a) {
+              gp[a] += w * cc[a] * vp;
+              gl[a] += w * cc[a] * vl;
+              if (!f) wt[a] += w * cc[a];
+            }
           }
         }
 #pragma unroll
         for (int a = 0; a < D; ++a)
-          F[a] = 2.0 * p0 * (3.0 * gp[a]) + I.mp_kappa * rho * (3.0 * gl[a]) +
-                 I.mp_kappa_w * rho * wt[a];
+          F[a] = 2.0 * p0 * (3.0 * gp[a]) + I.mp_kappa * rho0 * (3.0 * gl[a]) +
+                 I.mp_kappa_w * rho0 * wt[a];
       }
-      // ---- forced collision (FP64) -------------------------------------------
-      const double ir = 1.0 / rho;
-      const double u[3] = {j[0] * ir, j[1] * ir, j[2] * ir};
-      const double us[3] = {u[0] + F[0] * ir, u[1] + F[1] * ir, u[2] + F[2] * ir};
-      bool ok = rho > 0.0 && isfinite(rho);
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-        ok = ok && fabs(u[a]) < 1.0 && fabs(us[a]) < 1.0 && isfinite(us[a]);
-      if (!ok) {
+      // ---- forced collision (FP64) ---------------------------------------------
+      // The state in its storage type (FP32 or FP64; multiphase needs one of
+      // the two), in place; the arithmetic in FP64.
+      float g;
+      if (!collide_forced<Q, T>(db + node, stride, F, I.beta, I.collision, I.trace_in_s, g)) {
         atomicOr(b.err, 1u);
         continue;
       }
-      const AxisEq<double> ax = axis_eq(u[0]), ay = axis_eq(u[1]);
-      const AxisEq<double> az = Q == 27 ? axis_eq(u[2]) : ay;
-      const AxisEq<double> sx = axis_eq(us[0]), sy = axis_eq(us[1]);
-      const AxisEq<double> sz = Q == 27 ? axis_eq(us[2]) : sy;
-      // Second moments of Delta = f - f^eq(rho, u).
-      double Pxx = 0.0, Pyy = 0.0, Pzz = 0.0, Pxy = 0.0, Pxz = 0.0, Pyz = 0.0;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const double dl = d[i] - eq_dev_at<Q>(i, rt, rho, ax, ay, az);
-        if (cx(i)) Pxx += dl;
-        if (cy(i)) Pyy += dl;
-        if (cz<Q>(i)) Pzz += dl;
-        Pxy += (double)(cx(i) * cy(i)) * dl;
-        Pxz += (double)(cx(i) * cz<Q>(i)) * dl;
-        Pyz += (double)(cy(i) * cz<Q>(i)) * dl;
-      }
-      double Tr, Dxx, Dyy, Dzz;
-      if (Q == 27) {
-        Tr = Pxx + Pyy + Pzz;
-        Dxx = Pxx - Tr / 3.0;
-        Dyy = Pyy - Tr / 3.0;
-        Dzz = -(Dxx + Dyy);
-      } else {
-        Tr = Pxx + Pyy;
-        Dxx = 0.5 * (Pxx - Pyy);
-        Dyy = -Dxx;
-        Dzz = 0.0;
-      }
-      const double ts = I.trace_in_s ? Tr : 0.0;
-      auto s_of = [&](int i) -> double {
-        const int c0 = cx(i), c1 = cy(i), c2 = cz<Q>(i);
-        const int nzc = (c0 != 0) + (c1 != 0) + (c2 != 0);
-        if (nzc == 1) return 0.5 * (c0 != 0 ? Dxx : (c1 != 0 ? Dyy : Dzz)) + ts * (0.5 / D);
-        if (nzc == 2) return 0.25 * (c0 * c1 * Pxy + c0 * c2 * Pxz + c1 * c2 * Pyz);
-        if (nzc == 0) return -ts;
-        return 0.0;
-      };
-      double aa = 0.0, bb = 0.0;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const double dl = d[i] - eq_dev_at<Q>(i, rt, rho, ax, ay, az);
-        const double si = s_of(i), hi = dl - si;
-        const double inv = 1.0 / (weight<Q>(i) + eq_dev_at<Q>(i, rt, rho, sx, sy, sz));
-        aa += si * hi * inv;
-        bb += hi * hi * inv;
-      }
-      double gamma = 2.0;
-      if (!I.collision && bb != 0.0) gamma = 1.0 / beta - (2.0 - 1.0 / beta) * aa / bb;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const double fe = eq_dev_at<Q>(i, rt, rho, ax, ay, az);
-        const double fs = eq_dev_at<Q>(i, rt, rho, sx, sy, sz);
-        const double si = s_of(i), hi = (d[i] - fe) - si;
-        db[i * stride + node] = S::enc_d(d[i] - beta * (2.0 * si + gamma * hi) + (fs - fe));
-      }
-      gmin = fminf(gmin, (float)gamma);
-      gmax = fmaxf(gmax, (float)gamma);
-      gsum += gamma;
+      gmin = fminf(gmin, g);
+      gmax = fmaxf(gmax, g);
+      gsum += g;
       cnt += 1;
     }
   }

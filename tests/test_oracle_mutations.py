@@ -150,6 +150,10 @@ CASES = [
      "      a += ds[i] * dh[i] / feqs[i];\n      b += dh[i] * dh[i] / feqs[i];",
      "      a += ds[i] * dh[i] / feq[i];\n      b += dh[i] * dh[i] / feq[i];",
      "test_oracle_multiphase:test_shifted_gamma_minimises_shifted_entropy_norm", (27,)),
+    # Multiphase wall fill without the bounce-back mass.
+    ("mp_fill_unscaled",
+     "          const double lam = (rho_t - sk) / sm;", "          const double lam = 1.0;",
+     "test_oracle_multiphase:test_droplet_on_non_wetting_wall_keeps_its_mass", ()),
     # Exact difference method with half the velocity increment.
     ("mp_edm_half_increment",
      "    us[a] = u[a] + F[a] / rho;", "    us[a] = u[a] + 0.5 * F[a] / rho;",

@@ -270,3 +270,25 @@ def circle_polygon(center, radius, count=64):
     V[:, 1] = center[1] + radius * np.sin(th)
     T = np.stack([np.arange(count), (np.arange(count) + 1) % count, np.arange(count)], 1)
     return V, T.astype(np.int64)
+
+
+def droplet_impact(nx=320, ny=250, nz=320, diameter=80.0, gap=4.0, u_impact=0.02, width=2.0,
+                   rho_l=7.52, rho_v=0.073):
+    """Multiphase droplet-impact setup of Sec. III.B: a liquid droplet of the
+    given diameter (80 lattice spacings, domain 320 x 250 x 320 as in the
+    paper) centred over the middle of a wall at the bottom (-y) face, its
+    lowest point `gap` spacings above the first node row, moving towards the
+    wall at u_impact inside the droplet; vapour at rest elsewhere.  The
+    interface is a tanh profile of the given width between the flat-interface
+    densities of the equation of state.  Returns (rho (N,), u (3, N), info);
+    faces: walls at -y and +y, periodic in x and z."""
+    R = 0.5 * diameter
+    c = (0.5 * (nx - 1), R + gap, 0.5 * (nz - 1))
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2).ravel()
+    phase = 0.5 * (1.0 - np.tanh((r - R) / width))
+    rho = rho_v + (rho_l - rho_v) * phase
+    u = np.zeros((3, rho.size))
+    u[1] = -u_impact * phase
+    faces = ["periodic", "periodic", "wall", "wall", "periodic", "periodic"]
+    return rho, u, dict(centre=c, radius=R, faces=faces)
