@@ -544,6 +544,32 @@ void mesh_velocity(const Body& b, int D, const double* x, double* v) {
   if (D == 2) v[2] = 0.0;
 }
 
+// Smallest squared distance from x to the faces of the mesh (D = 2: the
+// segments of the first two vertices).
+double mesh_dist2(const Body& b, int D, const double* x) {
+  double best = 1e300;
+  const size_t nt = b.mt.size() / 3;
+  for (size_t k = 0; k < nt; ++k) {
+    const int i0 = b.mt[3 * k], i1 = b.mt[3 * k + 1], i2 = b.mt[3 * k + 2];
+    double r;
+    if (D == 3) {
+      double l[3];
+      r = closest_on_triangle(&b.mv[3 * i0], &b.mv[3 * i1], &b.mv[3 * i2], x, l);
+    } else {
+      const double* p0 = &b.mv[3 * i0];
+      const double* p1 = &b.mv[3 * i1];
+      const double ex = p1[0] - p0[0], ey = p1[1] - p0[1];
+      const double len2 = ex * ex + ey * ey;
+      double s = len2 > 0.0 ? ((x[0] - p0[0]) * ex + (x[1] - p0[1]) * ey) / len2 : 0.0;
+      s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
+      const double dx = p0[0] + s * ex - x[0], dy = p0[1] + s * ey - x[1];
+      r = dx * dx + dy * dy;
+    }
+    best = std::min(best, r);
+  }
+  return best;
+}
+
 bool body_inside(const Body& b, int D, const double* x, double t) {
   switch (b.kind) {
     case 1: {
@@ -561,7 +587,10 @@ bool body_inside(const Body& b, int D, const double* x, double t) {
       return std::fabs(x[0] - xc) <= 0.5 * b.p[2];
     }
     case 3:
-      return std::fabs(D == 3 ? winding_3d(b, x) : winding_2d(b, x)) > 0.5;
+      // Inside, or on the surface (where the winding number is exactly 1/2,
+      // so the surface test is explicit).
+      return std::fabs(D == 3 ? winding_3d(b, x) : winding_2d(b, x)) > 0.5 ||
+             mesh_dist2(b, D, x) <= 1e-24;
     case 4:
       return x[1] < b.p[0] || x[1] > b.p[1];
     default:

@@ -158,3 +158,26 @@ def test_mesh_velocity_at_closest_point_of_a_box(orc):
     for p in P:
         v = d.body_velocity(p)
         assert np.max(np.abs(v - field(np.clip(p, lo, hi)))) < 1e-12, p
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_nodes_on_the_surface_are_solid(orc, Q):
+    """Faces through lattice nodes (integer bounds): the nodes on the faces,
+    edges and corners count as solid, so the solid set is the closed box."""
+    if Q == 27:
+        n = 9
+        lo, hi = (1.0, 2.0, 1.0), (5.0, 6.0, 4.0)
+        V, T = W.cube_mesh(lo, hi)
+        d = orc.Domain(27, n, n, n, 0.05)
+        X = _grid(n, n, n)
+    else:
+        n = 12
+        lo, hi = (2.0, 3.0), (9.0, 8.0)
+        V = np.array([[lo[0], lo[1], 0], [hi[0], lo[1], 0], [hi[0], hi[1], 0], [lo[0], hi[1], 0]],
+                     dtype=float)
+        T = np.array([[0, 1, 0], [1, 2, 1], [2, 3, 2], [3, 0, 3]])
+        d = orc.Domain(9, n, n, 1, 0.05)
+        X = _grid(n, n, 1)[:, :2]
+    d.set_mesh(V, np.zeros_like(V), T)
+    box = np.all((X >= lo) & (X <= hi), axis=1)
+    assert np.array_equal(d.solid().astype(bool), box)

@@ -117,6 +117,11 @@ CASES = [
      "      const double s = A > 0.0 ? clamp01(-Dv / A) : 0.0;",
      "      const double s = A > 0.0 ? -Dv / A : 0.0;",
      "test_oracle_mesh:test_mesh_velocity_at_closest_point_of_a_box", ()),
+    # Mesh solid test without the explicit surface rule.
+    ("mesh_surface_not_solid",
+     "      return std::fabs(D == 3 ? winding_3d(b, x) : winding_2d(b, x)) > 0.5 ||\n             mesh_dist2(b, D, x) <= 1e-24;",
+     "      return std::fabs(D == 3 ? winding_3d(b, x) : winding_2d(b, x)) > 0.5;",
+     "test_oracle_mesh:test_nodes_on_the_surface_are_solid", (9,)),
     # Korteweg term with the sign printed in the paper's reduced form.
     ("mp_kappa_sign",
      "2.0 * phi[n] * (3.0 * gphi[a]) + d.kappa * rho[n] * (3.0 * glap[a]) +",
@@ -187,6 +192,60 @@ def test_planted_mistake_fails_a_pin(tmp_path, name, orig, planted, pin, args):
     msrc.write_text(src.replace(orig, planted))
     code = CHILD.format(root=ROOT, tests=os.path.join(ROOT, "tests"), src=str(msrc),
                         lib=str(tmp_path / ("mut_%s.so" % name)), pin=pin, args=tuple(args))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "PIN FAILED" in r.stdout, "planted mistake %s was not caught by %s" % (name, pin)
+
+
+# Planted mistakes in the Python parts of the oracle (the beam and the
+# coupling): (module file, original text, planted text, pin module:function).
+PY_CASES = [
+    ("fsi_reference_pressure_as_load", "fsi.py",
+     "tr = np.asarray(tr).reshape(-1, 2) + nrm / 3.0", "tr = np.asarray(tr).reshape(-1, 2)",
+     "test_oracle_fsi:test_fluid_at_rest_leaves_the_beam_at_rest"),
+    ("fsi_normal_inward", "fsi.py",
+     "nrm.append(np.array([t[1], -t[0]]) / L)", "nrm.append(np.array([-t[1], t[0]]) / L)",
+     "test_oracle_fsi:test_wet_edge_quadrature_of_the_undeformed_beam"),
+    ("fem_tangent_without_geometric_term", "fem.py",
+     "        dP = geo + mat", "        dP = mat",
+     "test_oracle_fem:test_tangent_is_derivative_of_internal_force"),
+    ("fem_green_strain_linearised", "fem.py",
+     "        E = 0.5 * (np.einsum(\"egkI,egkJ->egIJ\", F, F) - np.eye(2))\n        trE",
+     "        E = 0.5 * (G + np.swapaxes(G, -1, -2))\n        trE",
+     "test_oracle_fem:test_csm3_tip_motion_matches_printed"),
+]
+
+PY_CHILD = textwrap.dedent("""
+    import importlib.util, sys, types
+    sys.path.insert(0, {root!r}); sys.path.insert(0, {tests!r})
+    import oracle
+    spec = importlib.util.spec_from_file_location("oracle.{mod}", {path!r})
+    m = importlib.util.module_from_spec(spec)
+    sys.modules["oracle.{mod}"] = m
+    spec.loader.exec_module(m)
+    setattr(oracle, "{mod}", m)
+    import importlib
+    mod, _, fn = {pin!r}.rpartition(":")
+    T = importlib.import_module(mod)
+    import inspect
+    f = getattr(T, fn)
+    try:
+        f(*([oracle] if "orc" in inspect.signature(f).parameters else []))
+    except AssertionError:
+        print("PIN FAILED")
+        sys.exit(0)
+    print("PIN PASSED")
+""")
+
+
+@pytest.mark.parametrize("name,fname,orig,planted,pin", PY_CASES, ids=[c[0] for c in PY_CASES])
+def test_planted_mistake_in_python_oracle_fails_a_pin(tmp_path, name, fname, orig, planted, pin):
+    src = open(os.path.join(ROOT, "oracle", fname)).read()
+    assert src.count(orig) == 1, "the text to mutate must occur exactly once"
+    p = tmp_path / fname
+    p.write_text(src.replace(orig, planted))
+    code = PY_CHILD.format(root=ROOT, tests=os.path.join(ROOT, "tests"), mod=fname[:-3],
+                           path=str(p), pin=pin)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
     assert "PIN FAILED" in r.stdout, "planted mistake %s was not caught by %s" % (name, pin)
