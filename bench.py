@@ -345,6 +345,58 @@ def multiphase_workload(lbm, torch, args):
             "forms": out}
 
 
+def fsi3_workload(lbm, torch, args):
+    """FSI3 (Sec. III.A.1) at uniform resolution D = 40: the D2Q9 KBC fluid
+    in FP64 on the GPU coupled every step with the FEM beam (lbm_fsi_step).
+    Reports the tip displacement of the flag (point A, mid-height of the free
+    end) over the last window: mean and amplitude of u_x and u_y in metres and
+    their frequencies in Hz, beside the values the paper prints."""
+    import workloads as W
+
+    cfg = W.fsi3()
+    nx, ny = cfg["nx"], cfg["ny"]
+    s = lbm.Solver([dict(Q=9, nx=nx, ny=ny, nz=1, nu=cfg["nu"], storage="f64",
+                         faces=cfg["faces"], u_in=(cfg["u_mean"], 0.0, 0.0), inlet_profile=1,
+                         ramp_steps=cfg["ramp_steps"])])
+    N = nx * ny
+    s.init_fields(np.ones(N), np.zeros((2, N)))
+    beam = lbm.Beam(*cfg["beam"])
+    cp = lbm.Coupling(s, beam, cfg["arc"])
+    sps = cfg["steps_per_second"]
+    total = int(round(args.fsi_seconds * sps))
+    chunk = sps // 10
+    tips, t0 = [], time.perf_counter()
+    done = 0
+    while done < total:
+        k = min(chunk, total - done)
+        _, tip = cp.step(k)
+        tips.append(tip)
+        done += k
+        print("fsi3: t = %.2f s, tip (%.5f, %.5f) m, %.2f ms per coupled step"
+              % (done / sps, tip[-1, 0] * cfg["dx"], tip[-1, 1] * cfg["dx"],
+                 (time.perf_counter() - t0) * 1e3 / done), file=sys.stderr, flush=True)
+    el = time.perf_counter() - t0
+    tip = np.concatenate(tips) * cfg["dx"]
+    out = {"metric": "FSI3 flag tip displacement (mean +- amplitude) and frequency",
+           "config": {"workload": "FSI3, D2Q9 KBC FP64 1000x164 (D = 40) coupled every step "
+                                  "with a 20 x 2 nine-node SVK beam, %.1f s simulated" % args.fsi_seconds},
+           "ms_per_coupled_step": round(el * 1e3 / total, 4),
+           "paper": {"ux": [-0.00268, 0.00257], "uy": [0.00145, 0.03380], "fx_Hz": 11, "fy_Hz": 5.5}}
+    w = tip[-int(args.fsi_window * sps):] if args.fsi_window * sps < len(tip) else tip
+    res = {}
+    for a, name in ((0, "ux"), (1, "uy")):
+        x = w[:, a]
+        m, amp = (x.max() + x.min()) / 2, (x.max() - x.min()) / 2
+        y = x - m
+        up = np.where((y[:-1] < 0) & (y[1:] >= 0))[0]
+        f = (len(up) - 1) / ((up[-1] - up[0]) / sps) if len(up) > 1 else None
+        res[name] = [round(float(m), 6), round(float(amp), 6)]
+        res["f" + name[-1] + "_Hz"] = round(f, 3) if f else None
+    out["present"] = res
+    out["tip_series_every_100_steps"] = [[round(float(v), 7) for v in r] for r in tip[::100]]
+    return out
+
+
 def tg512_workload(lbm, torch, args):
     """Config: D3Q27 TG 512^3, Re=1600: MLUPS and HBM fraction per storage form,
     velocity error of each against the FP64 form at steps 100 and 1000."""
@@ -471,8 +523,10 @@ def main():
     ap.add_argument("--variant", default=None, help="bulk-kernel variant (default: autotune)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64"])
     ap.add_argument("--mp-steps", type=int, default=200)
+    ap.add_argument("--fsi-seconds", type=float, default=8.0)
+    ap.add_argument("--fsi-window", type=float, default=2.0)
     ap.add_argument("--workload", default="tg256",
-                    choices=["tg256", "tg512", "sphere", "batched", "multiphase"],
+                    choices=["tg256", "tg512", "sphere", "batched", "multiphase", "fsi3"],
                     help="tg256 is the headline line; the others print their own line")
     ap.add_argument("--sphere-steps", type=int, default=1200)
     ap.add_argument("--sphere-sample", type=int, default=200)
@@ -502,6 +556,9 @@ def main():
                           "unit": "MLUPS", "config": {"workload": "64 D2Q9 KBC flap channels "
                                                       "(seed 2375), FP32"}, "forms": r}),
               flush=True)
+        return
+    if args.workload == "fsi3":
+        print(json.dumps(fsi3_workload(lbm, torch, args)), flush=True)
         return
     if args.workload == "multiphase":
         print(json.dumps(multiphase_workload(lbm, torch, args)), flush=True)

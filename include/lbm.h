@@ -247,6 +247,67 @@ lbm_status lbm_wall_force_noalloc(lbm_ctx* ctx, int inst, const double* xq, cons
  * FP32) for all instances.  Synchronous. */
 lbm_status lbm_set_multiphase(lbm_ctx* ctx, int inst, int enable, double kappa, double kappa_w);
 
+/* ---- Structure solver and two-way coupling (Sec. II.B, II.C) ------------
+ * A rectangular beam [x0, x0 + length] x [y0, y0 + height] in plane strain:
+ * total-Lagrangian Saint Venant-Kirchhoff material (Sec. II.B: P = F S,
+ * S = lambda tr(E) I + 2 mu E, E = (F^T F - I)/2), nex x ney 9-node
+ * biquadratic elements with 3 x 3 Gauss points, consistent mass, the
+ * two-field (u, v) formulation with the one-step-theta scheme (theta = 1/2:
+ * Crank-Nicolson) solved by Newton's method.  The edge x = x0 is clamped.
+ * Node (i, j), 0 <= i <= 2 nex, 0 <= j <= 2 ney, has index j + (2 ney + 1) i
+ * and DOFs 2 k (x), 2 k + 1 (y).  Units are the caller's (lattice units when
+ * coupled).  Host code; the beam has ~10^2-10^3 unknowns. */
+typedef struct lbm_fem lbm_fem;
+typedef struct {
+  double x0, y0, length, height;
+  int nex, ney;
+  double rho, lambda, mu;   /* density, Lame coefficients */
+  double dt, theta;
+} lbm_fem_desc;
+/* Errors: LBM_ERR_INVALID for a bad description. */
+lbm_status lbm_fem_create(const lbm_fem_desc* desc, lbm_fem** out);
+lbm_status lbm_fem_destroy(lbm_fem* fem);
+/* Node count, and (if coords is not NULL) the 2 * nodes reference
+ * coordinates. */
+lbm_status lbm_fem_info(const lbm_fem* fem, int* nodes, double* coords);
+/* Consistent nodal loads (2 * nodes doubles into f) of a uniform body force
+ * b per unit mass. */
+lbm_status lbm_fem_body_force(const lbm_fem* fem, const double b[2], double* f);
+/* One theta step with the external nodal loads fext (2 * nodes doubles) at
+ * the new time (the previous step's loads are kept as the old time level's).
+ * iterations (may be NULL) receives the Newton count.  Returns
+ * LBM_ERR_NONFINITE if Newton does not converge in 30 iterations. */
+lbm_status lbm_fem_step(lbm_fem* fem, const double* fext, int* iterations);
+/* Displacements u and velocities v (2 * nodes doubles each; either may be
+ * NULL). */
+lbm_status lbm_fem_get_state(const lbm_fem* fem, double* u, double* v);
+lbm_status lbm_fem_set_state(lbm_fem* fem, const double* u, const double* v);
+
+/* Two-way coupling of instance inst (2D) with a beam, by the conventional
+ * serial staggered scheme of Sec. II.C.  The body of the instance becomes a
+ * closed polygon (LBM_BODY_MESH): the beam's wet boundary (bottom edge from
+ * the clamped end to the tip, the tip, the top edge back), in its current
+ * position and velocity, then the static chain arc (n_arc points, 2 doubles
+ * each, from the clamped top corner round to the clamped bottom corner,
+ * both excluded; n_arc = 0 closes the beam along its clamped edge).  Each
+ * coupled step: lbm_step; the traction of the fluid on the beam at the three
+ * Gauss points of every quadratic wet edge in its current position
+ * (lbm_wall_force_noalloc, Sec. II.C.2), less the reference pressure
+ * rho_0 c_s^2 = 1/3 (the beam is only partly wet, so a uniform pressure does
+ * not cancel on it); lbm_fem_step with the consistent
+ * nodal loads sum_q N_a t_q w_q; the polygon set from the new state for the
+ * next step.  fem must outlive the coupling; the context and instance must
+ * be 2D.  Errors: those of lbm_set_geometry at creation. */
+typedef struct lbm_fsi lbm_fsi;
+lbm_status lbm_fsi_create(lbm_ctx* ctx, int inst, lbm_fem* fem, const double* arc, int n_arc,
+                          lbm_fsi** out);
+lbm_status lbm_fsi_destroy(lbm_fsi* fsi);
+/* n_steps coupled steps.  beam_force (3 doubles per step, may be NULL): the
+ * force of the fluid on the beam's wet edges (gauge pressure); tip (2 per step, may be NULL):
+ * the displacement of the node at mid-height of the free end.  Stops at the
+ * first error (LBM_ERR_NONFINITE from the fluid or the structure). */
+lbm_status lbm_fsi_step(lbm_fsi* fsi, int n_steps, double* beam_force, double* tip);
+
 /* Checkpoint: copies the populations of instance inst to / from the host
  * (Q*N doubles, population-major, full f_i).  A set is rounded to the
  * storage format.  Resuming from get -> set is bitwise exact. */

@@ -5,7 +5,8 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = [os.path.join(HERE, "csrc", "kernels.hip"), os.path.join(HERE, "csrc", "engine.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "kernels.hip"), os.path.join(HERE, "csrc", "engine.hip"),
+           os.path.join(HERE, "csrc", "fsi.hip")]
 HEADERS = [os.path.join(HERE, "csrc", n) for n in ("lbm_device.hpp", "kbc_node.hpp", "kernels.hpp")]
 LIB = os.path.join(HERE, "libkbc_lbm.so")
 ARCH = os.environ.get("KBC_OFFLOAD_ARCH", "gfx950")

@@ -59,7 +59,7 @@ __device__ __forceinline__ bool resolve_nb(const InstDev& I, int x, int y, int z
 // ---------------------------------------------------------------------------
 // Solid when the line of the node's column crosses the surface an odd
 // number of times before x, or at x (surface points are solid).
-__device__ bool mesh_inside(const InstDev& I, int x, int y, int z) {
+__device__ bool mesh_parity(const InstDev& I, int x, int y, int z) {
   const int a = y - I.col_lo[0], b = z - I.col_lo[1];
   if (a < 0 || b < 0 || a >= I.col_n[0] || b >= I.col_n[1]) return false;
   const int k = a + I.col_n[0] * b;
@@ -174,6 +174,29 @@ __device__ double mesh_closest(const InstDev& I, int f, const double (&p)[3], do
 
 // Velocity at the closest surface point to p: faces of the cells within two
 // spacings of p, all faces if none is there.
+// Inside or on the surface.  The crossing count decides inside; a node the
+// count leaves outside is on the surface if a face of its bin passes within
+// 1e-12 of it (a face lying along the node's column, or the half-open tie
+// rule at an edge, gives no crossing at the node itself).
+__device__ bool mesh_inside(const InstDev& I, int x, int y, int z) {
+  if (mesh_parity(I, x, y, z)) return true;
+  const double p[3] = {(double)x, (double)y, (double)z};
+  const double lo[3] = {p[0] - 1e-9, p[1] - 1e-9, p[2] - 1e-9};
+  const double hi[3] = {p[0] + 1e-9, p[1] + 1e-9, p[2] + 1e-9};
+  int c0[3], c1[3];
+  mesh_cells(I, lo, hi, c0, c1);
+  for (int kz = c0[2]; kz <= c1[2]; ++kz)
+    for (int ky = c0[1]; ky <= c1[1]; ++ky)
+      for (int kx = c0[0]; kx <= c1[0]; ++kx) {
+        const int k = kx + I.bin_n[0] * (ky + I.bin_n[1] * kz);
+        for (int j = I.bin_start[k]; j < I.bin_start[k + 1]; ++j) {
+          double l[3];
+          if (mesh_closest(I, I.bin_face[j], p, l) <= 1e-24) return true;
+        }
+      }
+  return false;
+}
+
 __device__ void mesh_velocity(const InstDev& I, const double (&p)[3], double (&v)[3]) {
   double lo[3], hi[3];
   for (int a = 0; a < 3; ++a) {

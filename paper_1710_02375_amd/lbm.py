@@ -53,6 +53,13 @@ class lbm_body(C.Structure):
                 ("tris", C.c_void_p)]
 
 
+class lbm_fem_desc(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("length", C.c_double),
+                ("height", C.c_double), ("nex", C.c_int), ("ney", C.c_int), ("rho", C.c_double),
+                ("lambda_", C.c_double), ("mu", C.c_double), ("dt", C.c_double),
+                ("theta", C.c_double)]
+
+
 class lbm_totals(C.Structure):
     _fields_ = [("mass", C.c_double), ("momentum", C.c_double * 3), ("gamma_min", C.c_double),
                 ("gamma_mean", C.c_double), ("gamma_max", C.c_double),
@@ -101,6 +108,16 @@ def lib():
         L.lbm_get_populations_box.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                               _dp]
         L.lbm_set_multiphase.argtypes = [vp, C.c_int, C.c_int, C.c_double, C.c_double]
+        L.lbm_fem_create.argtypes = [C.POINTER(lbm_fem_desc), C.POINTER(C.c_void_p)]
+        L.lbm_fem_destroy.argtypes = [vp]
+        L.lbm_fem_info.argtypes = [vp, C.POINTER(C.c_int), vp]
+        L.lbm_fem_body_force.argtypes = [vp, _dp, _dp]
+        L.lbm_fem_step.argtypes = [vp, _dp, C.POINTER(C.c_int)]
+        L.lbm_fem_get_state.argtypes = [vp, vp, vp]
+        L.lbm_fem_set_state.argtypes = [vp, vp, vp]
+        L.lbm_fsi_create.argtypes = [vp, C.c_int, vp, vp, C.c_int, C.POINTER(C.c_void_p)]
+        L.lbm_fsi_destroy.argtypes = [vp]
+        L.lbm_fsi_step.argtypes = [vp, C.c_int, vp, vp]
         L.lbm_set_stats.argtypes = [vp, C.c_int]
         L.lbm_set_launch_mode.argtypes = [vp, C.c_int]
         L.lbm_autotune.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int)]
@@ -122,6 +139,9 @@ def lib():
 EXPORTED = ["lbm_create", "lbm_destroy", "lbm_init_fields", "lbm_set_geometry", "lbm_step",
             "lbm_moments", "lbm_wall_force", "lbm_wall_force_noalloc", "lbm_get_populations",
             "lbm_set_populations", "lbm_get_populations_box", "lbm_set_multiphase",
+            "lbm_fem_create", "lbm_fem_destroy", "lbm_fem_info", "lbm_fem_body_force",
+            "lbm_fem_step", "lbm_fem_get_state", "lbm_fem_set_state", "lbm_fsi_create",
+            "lbm_fsi_destroy", "lbm_fsi_step",
             "lbm_set_stats", "lbm_set_launch_mode", "lbm_autotune", "lbm_set_variant",
             "lbm_variant_count", "lbm_variant_name", "lbm_info", "lbm_synchronize",
             "lbm_status_string", "lbm_last_error"]
@@ -321,6 +341,84 @@ def lbm_set_multiphase(ctx, inst, kappa, kappa_w=0.0, enable=True):
     """Multiphase forcing of Sec. III.B on instance inst (or off)."""
     return _check(ctx, lib().lbm_set_multiphase(ctx, int(inst), int(bool(enable)), float(kappa),
                                                 float(kappa_w)))
+
+
+class Beam:
+    """Finite-element beam of the structure solver (lbm_fem_*): Sec. II.B."""
+
+    def __init__(self, x0, y0, length, height, nex, ney, rho, lam, mu, dt, theta=0.5):
+        d = lbm_fem_desc(float(x0), float(y0), float(length), float(height), int(nex), int(ney),
+                         float(rho), float(lam), float(mu), float(dt), float(theta))
+        h = C.c_void_p()
+        _check(None, lib().lbm_fem_create(C.byref(d), C.byref(h)))
+        self.h = h
+        n = C.c_int(0)
+        lib().lbm_fem_info(self.h, C.byref(n), None)
+        self.nn = n.value
+        self.X = np.zeros(2 * self.nn)
+        lib().lbm_fem_info(self.h, None, self.X.ctypes.data_as(C.c_void_p))
+        self.X = self.X.reshape(-1, 2)
+        self.nex, self.ney = nex, ney
+
+    def body_force(self, b):
+        f = np.zeros(2 * self.nn)
+        _check(None, lib().lbm_fem_body_force(self.h, _f64(b), f))
+        return f
+
+    def step(self, fext):
+        it = C.c_int(0)
+        _check(None, lib().lbm_fem_step(self.h, _f64(fext), C.byref(it)))
+        return it.value
+
+    def state(self):
+        u, v = np.zeros(2 * self.nn), np.zeros(2 * self.nn)
+        lib().lbm_fem_get_state(self.h, u.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p))
+        return u, v
+
+    def set_state(self, u, v):
+        u, v = _f64(u), _f64(v)
+        lib().lbm_fem_set_state(self.h, u.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p))
+
+    def tip(self):
+        u, _ = self.state()
+        k = self.ney + (2 * self.ney + 1) * (2 * self.nex)
+        return u[2 * k: 2 * k + 2]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm_fem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Coupling:
+    """Two-way coupling of a context instance with a Beam (lbm_fsi_*): Sec. II.C."""
+
+    def __init__(self, solver, beam, arc=None, inst=0):
+        a = _f64(arc) if arc is not None and len(arc) else np.zeros(0)
+        h = C.c_void_p()
+        _check(solver.ctx, lib().lbm_fsi_create(solver.ctx, int(inst), beam.h,
+                                               a.ctypes.data_as(C.c_void_p) if a.size else None,
+                                               a.size // 2, C.byref(h)))
+        self.h, self.solver, self.beam = h, solver, beam
+
+    def step(self, n=1):
+        """n coupled steps; returns (beam force (n, 3), tip displacement (n, 2))."""
+        F = np.zeros(3 * n)
+        tip = np.zeros(2 * n)
+        _check(self.solver.ctx, lib().lbm_fsi_step(self.h, int(n), F.ctypes.data_as(C.c_void_p),
+                                                  tip.ctypes.data_as(C.c_void_p)))
+        return F.reshape(n, 3), tip.reshape(n, 2)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm_fsi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 def lbm_set_stats(ctx, enabled):

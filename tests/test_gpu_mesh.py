@@ -171,3 +171,22 @@ def test_mesh_errors():
     with pytest.raises(lbm.LBMError) as ei:
         s.set_body(lbm.LBM_BODY_MESH, verts=V + 6.0, vert_vel=np.zeros_like(V), tris=T)
     assert ei.value.status == lbm.LBM_ERR_GEOMETRY
+
+
+def test_faces_through_nodes_f64():
+    """A polygon whose edges pass through lattice nodes (integer bounds) in a
+    channel: nodes on the surface are solid on both sides, and the cut links
+    that end on them (q = 1) agree with the oracle."""
+    nx, ny = 40, 24
+    V = np.array([[12.0, 8.0, 0], [22.0, 8.0, 0], [22.0, 15.0, 0], [12.0, 15.0, 0]])
+    T = np.array([[0, 1, 0], [1, 2, 1], [2, 3, 2], [3, 0, 3]], dtype=np.int32)
+    say("case: square polygon with edges through nodes, F64 %dx%d" % (nx, ny))
+    s, d = _pair(9, nx, ny, 1, 0.05, faces=["inlet", "outlet", "wall", "wall", "periodic",
+                                              "periodic"], u_in=(0.03, 0, 0), ramp_steps=10)
+    _set_mesh(s, d, V, np.zeros_like(V), T)
+    solid_g = s.moments()[0] == 0
+    assert np.array_equal(solid_g, d.solid() == 1), (int(solid_g.sum()), int(d.solid().sum()))
+    for k in (1, 10):
+        s.step(k)
+        d.step(k)
+        _compare(s, d, 1e-12, "t=%d" % d.time)
