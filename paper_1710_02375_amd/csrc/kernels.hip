@@ -455,8 +455,10 @@ __device__ __forceinline__ void lagged(const typename Store<ST>::T* sb, int64_t 
 //   t1   : time of the new state (geometry and inflow ramp)
 // Returns the deviations f_i - W_i.  Each neighbour's lagged moments are
 // read only where the chosen interpolation or difference uses them.
+// WALLONLY: every missing population of the node comes from a wall face
+// (q = 1/2, wall at rest), so the body cut-link code is not compiled in.
 // ---------------------------------------------------------------------------
-template <int Q, int ST, typename R>
+template <int Q, int ST, typename R, bool WALLONLY = false>
 __device__ void gather_pre(const InstDev& I, const typename Store<ST>::T* sb, const uint8_t* fl,
                            int x, int y, int z, double t1, R (&f)[Q]) {
   using S = Store<ST>;
@@ -518,7 +520,7 @@ __device__ void gather_pre(const InstDev& I, const typename Store<ST>::T* sb, co
   // ---- Grad's approximation for the missing populations ----------------
   const double tq = t1;
   auto link = [&](int i, R& q, R (&uw)[3]) {
-    if ((wallm >> i) & 1u) {
+    if (WALLONLY || ((wallm >> i) & 1u)) {
       q = R(0.5);
       uw[0] = uw[1] = uw[2] = R(0);
     } else {
@@ -1136,7 +1138,9 @@ __global__ void __launch_bounds__(64) k_boundary_wall(StepBuffers b, const uint2
     const uint8_t* fl = b.flags + I.flag_off;
     const Coord c = node_coord(I, e.y);
     double f[Q];
-    gather_pre<Q, ST, double>(I, sb, fl, c.x, c.y, c.z, t1, f);
+    // Every missing population of these nodes comes from a wall face (q = 1/2,
+    // at rest): the body cut-link code is left out.
+    gather_pre<Q, ST, double, true>(I, sb, fl, c.x, c.y, c.z, t1, f);
     if constexpr (PRE) {
       // Multiphase: the pre-collision state and its density, for the forced
       // collision that follows.

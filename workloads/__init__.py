@@ -294,7 +294,7 @@ def droplet_impact(nx=320, ny=250, nz=320, diameter=80.0, gap=4.0, u_impact=0.02
     return rho, u, dict(centre=c, radius=R, faces=faces)
 
 
-def fsi3(d_lb=40, u_mean=0.05, nex=20, ney=2, arc_points=120, theta=0.55):
+def fsi3(d_lb=40, u_mean=0.035, nex=20, ney=2, arc_points=120, theta=0.55):
     """FSI3 of Sec. III.A.1 in lattice units: channel 2.5 x 0.41 m, cylinder
     of diameter D = 0.1 m at (0.2, 0.2) m, elastic flap 0.35 x 0.02 m clamped
     in it; rho_f = rho_s = 1e3 kg/m^3, nu_f = 1e-3 m^2/s, mean inflow 2 m/s
