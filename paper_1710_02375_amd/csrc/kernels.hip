@@ -320,7 +320,8 @@ __device__ void mesh_cut(const InstDev& I, int x, int y, int z, int c0, int c1, 
 // ---------------------------------------------------------------------------
 // Prescribed-motion bodies (FP64).  Time t is the step count.
 // ---------------------------------------------------------------------------
-__device__ bool body_inside(const InstDev& I, double x, double y, double z, double t) {
+// Analytic bodies (sphere, flap, plates) at an arbitrary point.
+__device__ bool analytic_inside(const InstDev& I, double x, double y, double z, double t) {
   const double* p = I.body;
   switch (I.body_kind) {
     case LBM_BODY_SPHERE: {
@@ -340,13 +341,17 @@ __device__ bool body_inside(const InstDev& I, double x, double y, double z, doub
       const double xc = p[0] + p[3] * sin(p[4] * t + p[5]) * (sl / p[1]) * (sl / p[1]);
       return fabs(x - xc) <= 0.5 * p[2];
     }
-    case LBM_BODY_MESH:
-      return mesh_inside(I, (int)x, (int)y, (int)z);
     case LBM_BODY_PLATES:
       return y < p[0] || y > p[1];
     default:
       return false;
   }
+}
+
+// Solid test of a lattice node (meshes by crossings and surface distance).
+__device__ bool body_inside(const InstDev& I, double x, double y, double z, double t) {
+  if (I.body_kind == LBM_BODY_MESH) return mesh_inside(I, (int)x, (int)y, (int)z);
+  return analytic_inside(I, x, y, z, t);
 }
 
 __device__ void body_velocity(const InstDev& I, double x, double y, double z, double t,
@@ -405,7 +410,7 @@ __device__ void body_cut(const InstDev& I, int x, int y, int z, int c0, int c1, 
     double lo = 0.0, hi = 1.0;
     for (int it = 0; it < 60; ++it) {
       const double mid = 0.5 * (lo + hi);
-      if (body_inside(I, x - mid * c0, y - mid * c1, z - mid * c2, t)) hi = mid; else lo = mid;
+      if (analytic_inside(I, x - mid * c0, y - mid * c1, z - mid * c2, t)) hi = mid; else lo = mid;
     }
     q = hi;
   }
@@ -457,8 +462,10 @@ __device__ __forceinline__ void lagged(const typename Store<ST>::T* sb, int64_t 
 // read only where the chosen interpolation or difference uses them.
 // WALLONLY: every missing population of the node comes from a wall face
 // (q = 1/2, wall at rest), so the body cut-link code is not compiled in.
+// MPFILL: compile in the multiphase scaling of the filled populations
+// (applied to multiphase instances only).
 // ---------------------------------------------------------------------------
-template <int Q, int ST, typename R, bool WALLONLY = false>
+template <int Q, int ST, typename R, bool WALLONLY = false, bool MPFILL = false>
 __device__ void gather_pre(const InstDev& I, const typename Store<ST>::T* sb, const uint8_t* fl,
                            int x, int y, int z, double t1, R (&f)[Q]) {
   using S = Store<ST>;
@@ -678,7 +685,7 @@ __device__ void gather_pre(const InstDev& I, const typename Store<ST>::T* sb, co
 #pragma unroll
   for (int i = 0; i < Q; ++i)
     if ((miss >> i) & 1u) f[i] = grad_dev<Q, R>(i, rho_t, ut, Pi);
-  if (I.mp) {
+  if (MPFILL && I.mp) {
     // Multiphase: the filled populations carry the mass that bounce-back
     // would return, rho_t less the known populations (scaled as full f).
     R sk = R(0), sm = R(0);
@@ -1140,7 +1147,7 @@ __global__ void __launch_bounds__(64) k_boundary_wall(StepBuffers b, const uint2
     double f[Q];
     // Every missing population of these nodes comes from a wall face (q = 1/2,
     // at rest): the body cut-link code is left out.
-    gather_pre<Q, ST, double, true>(I, sb, fl, c.x, c.y, c.z, t1, f);
+    gather_pre<Q, ST, double, true, PRE>(I, sb, fl, c.x, c.y, c.z, t1, f);
     if constexpr (PRE) {
       // Multiphase: the pre-collision state and its density, for the forced
       // collision that follows.
@@ -1459,11 +1466,12 @@ __global__ void __launch_bounds__(64) k_boundary_wave(StepBuffers b, const uint2
         d = grad_dev<Q, double>(i, rho_t, ut, Pi);
       }
     }
-    {
-      // Multiphase: the filled populations carry the mass that bounce-back
-      // would return, rho_t less the known populations (scaled as full f).
-      // The sums run on every wavefront so that the lane exchanges stay
-      // uniform; only multiphase instances apply them.
+    if constexpr (PRE) {
+      // Multiphase (only its pre-collision mode needs this): the filled
+      // populations carry the mass that bounce-back would return, rho_t less
+      // the known populations (scaled as full f).  The sums run on every
+      // wavefront so that the lane exchanges stay uniform; only multiphase
+      // instances apply them.
       const double fi = pop ? d + weight<Q>(i) : 0.0;
       const double sm = group_sum<GL>(pop && mi ? fi : 0.0);
       const double sk = group_sum<GL>(pop && !mi ? fi : 0.0);

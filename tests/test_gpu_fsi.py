@@ -80,3 +80,31 @@ def test_coupled_channel_f64_matches_oracle():
         assert du < 1e-9 and df < 1e-12
         assert np.allclose(Fg[-1][:2], Fo[:2], rtol=1e-9, atol=1e-14)
     assert np.abs(ob.u).max() > 1e-6   # the beam did move
+
+
+def test_fsi3_setup_runs_stably():
+    """The FSI3 configuration (1000x164 FP64 fluid, 20x2 beam, theta = 0.55)
+    for 0.1 s of physical time during the inflow ramp: the coupled steps stay
+    valid, the beam barely moves yet, and a step takes well under 2 ms."""
+    import time
+
+    import workloads as W
+    from paper_1710_02375_amd import lbm
+
+    c = W.fsi3()
+    s = lbm.Solver([dict(Q=9, nx=c["nx"], ny=c["ny"], nz=1, nu=c["nu"], storage="f64",
+                         faces=c["faces"], u_in=(c["u_mean"], 0, 0), inlet_profile=1,
+                         ramp_steps=c["ramp_steps"])])
+    N = c["nx"] * c["ny"]
+    s.init_fields(np.ones(N), np.zeros((2, N)))
+    b = lbm.Beam(*c["beam"])
+    cp = lbm.Coupling(s, b, c["arc"])
+    steps = c["steps_per_second"] // 10
+    t0 = time.perf_counter()
+    F, tip = cp.step(steps)
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    u, v = b.state()
+    say("  FSI3 %d coupled steps: %.3f ms per step, tip %s lu, max |v| %.2e" %
+        (steps, ms, tip[-1], np.abs(v).max()))
+    assert np.all(np.isfinite(tip)) and np.abs(tip).max() < 0.1 and np.abs(v).max() < 1e-3
+    assert ms < 2.0
