@@ -40,6 +40,13 @@ struct lbm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // Boundary kernels beside the bulk kernel: the scan, wavefront and wall
+  // kernels on `side`, forked from and joined back to `stream` every step
+  // (KBC_SERIAL_BOUNDARY=1 keeps everything on `stream`).  One side stream:
+  // a captured graph then has two branches, which run on two queues.
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool overlap = true;
   void* (*ualloc)(size_t, void*) = nullptr;
   void (*ufree)(void*, void*) = nullptr;
   void* actx = nullptr;
@@ -85,10 +92,11 @@ struct lbm_ctx {
   int64_t* dclock = nullptr;
   uint32_t* derr = nullptr;
   uint32_t* herr = nullptr;       // pinned mirror of the error word
-  uint32_t* dneq_count = nullptr; // two counters of deferred near-equilibrium nodes:
-                                  // a step with source buffer k appends to [k]
-  int last_src = -1;              // source buffer of the last step enqueued
-  uint2* dneq_list = nullptr;
+  // Near-equilibrium mask words (one per 64 nodes of a tile, the current
+  // tiling's layout), set by the bulk kernel, read and cleared by the FP64
+  // pass.
+  uint64_t* dneq_words = nullptr;
+  size_t neq_words_cap = 0;
   // Boundary node lists (two per launch: nodes with a cut link to a body,
   // then nodes whose missing populations all come from wall faces; inflow
   // and outflow plane nodes are formed by the bulk kernel): instance k's
@@ -410,6 +418,11 @@ lbm_status rebuild_work(lbm_ctx* c) {
     c->bl_total = off;
     c->bl_nwg_all = any_body ? nwg_for(off) : 0;
     c->bl_nwall_all = any_wall ? nwall_for(off) : 0;
+    // Side stream of the boundary kernels (default priority, like `stream`),
+    // made with the first boundary work: a periodic context has none.
+    if ((any_body || any_wall) && !c->side &&
+        hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess)
+      return fail(c, LBM_ERR_DEVICE, "hipStreamCreate failed");
     c->bstat_slots = std::max(c->bl_nwg_all + c->bl_nwall_all, sum_nwg);
     if ((size_t)off > c->dblist_cap) {
       dev_free(c, c->dblist);
@@ -448,6 +461,18 @@ lbm_status rebuild_tiles(lbm_ctx* c) {
   }
   lbm_status st = upload(c, &c->dtiles, c->tiles);
   if (st) return st;
+  // Mask words of the new tiling, cleared: the bulk kernel stores only words
+  // with a deferred node and the FP64 pass clears them, so they stay zero
+  // from here on (the FP64 pass also skips any bit beyond a tile's count).
+  const size_t nw = c->tiles.size() * (size_t)(tsz / 64);
+  if (nw > c->neq_words_cap) {
+    dev_free(c, c->dneq_words);
+    c->dneq_words = nullptr;
+    c->neq_words_cap = 0;
+    if ((st = dev_alloc(c, nw * sizeof(uint64_t), (void**)&c->dneq_words))) return st;
+    c->neq_words_cap = nw;
+  }
+  HIPCHECK(c, hipMemsetAsync(c->dneq_words, 0, c->neq_words_cap * sizeof(uint64_t), c->stream));
   if ((st = ensure_stats(c))) return st;
   invalidate_graphs(c);
   return LBM_OK;
@@ -463,13 +488,14 @@ lbm_status enqueue_step(lbm_ctx* c, int src) {
   b.err = c->derr;
   b.clock = c->dclock;
   b.stats = c->stats_enabled ? c->dstats : nullptr;
-  b.neq_count = c->dneq_count + src;
-  b.neq_next = c->dneq_count + (1 - src);
   b.clock_tick = c->time_dependent ? c->dclock : nullptr;
   b.bcount = c->dbcount;
   b.nbcount = 2 * (c->n_inst + 1);
-  b.neq_list = c->dneq_list;
-  b.neq_cap = (uint32_t)c->total_nodes;
+  // The multiphase pipeline defers nothing (FP64 collision throughout).
+  b.neq_words = c->dneq_words;
+  b.neq_wpt = (uint32_t)(bulk_variant_tile(c->variant) / 64);
+  b.neq_nwords = c->any_mp ? 0u : (uint32_t)c->tiles.size() * b.neq_wpt;
+  b.tiles = c->dtiles;
   const int ngt = (int)c->gtiles.size();
   if (ngt > 0)
     for (int stage = 0; stage < 3; ++stage)
@@ -481,14 +507,33 @@ lbm_status enqueue_step(lbm_ctx* c, int src) {
   // three multiphase passes stream, differentiate and collide.
   const bool mp = c->any_mp;
   if (c->launch_mode == 0) {
+    // The boundary kernels and the bulk kernel read the same source buffer
+    // and write disjoint nodes of the destination (the bulk kernel skips
+    // every node the scan can list): without the multiphase passes, which
+    // read what the boundary kernels write, they run side by side, the
+    // latency-bound boundary work under the bandwidth-bound bulk.  Both
+    // follow the geometry update (flags, refilled nodes); the FP64 pass
+    // follows both.
+    const bool fork = !mp && c->overlap && c->side && nbt > 0 &&
+                      (c->bl_nwg_all > 0 || c->bl_nwall_all > 0);
+    hipStream_t sb = c->stream;
+    if (fork) {
+      HIPCHECK(c, hipEventRecord(c->ev_fork, c->stream));
+      HIPCHECK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+      sb = c->side;
+    }
     HIPCHECK(c, c->ops->boundary(b, c->dregions, c->dbtiles, 0, nbt, c->dblist, c->bl_total,
                                  c->dbcount + 2 * c->n_inst, c->bl_nwg_all, c->bl_nwall_all, ntiles,
-                                 mp, c->stream));
+                                 mp, sb));
     if (mp) {
       for (int stage = 0; stage < 3; ++stage)
         HIPCHECK(c, c->ops->mp(stage, b, c->dtiles, 0, ntiles, c->stream));
     } else {
       HIPCHECK(c, c->ops->bulk(c->variant, b, c->dtiles, 0, ntiles, c->any_faces, c->stream));
+    }
+    if (fork) {
+      HIPCHECK(c, hipEventRecord(c->ev_join, c->side));
+      HIPCHECK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     }
   } else {
     for (int k = 0; k < c->n_inst; ++k) {
@@ -828,8 +873,7 @@ lbm_status lbm_destroy(lbm_ctx* c) {
   dev_free(c, c->dinst);
   dev_free(c, c->dclock);
   dev_free(c, c->derr);
-  dev_free(c, c->dneq_count);
-  dev_free(c, c->dneq_list);
+  dev_free(c, c->dneq_words);
   dev_free(c, c->dblist);
   dev_free(c, c->dbcount);
   dev_free(c, c->dtiles);
@@ -849,6 +893,12 @@ lbm_status lbm_destroy(lbm_ctx* c) {
   }
   if (c->herr) (void)hipHostFree(c->herr);
   if (c->err_event) (void)hipEventDestroy(c->err_event);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return LBM_OK;
@@ -978,25 +1028,25 @@ lbm_status lbm_create(const lbm_instance_desc* desc, int n_instances, const lbm_
   if ((st = dev_alloc(c, foff, (void**)&c->flags))) return bail(st);
   if ((st = dev_alloc(c, sizeof(int64_t), (void**)&c->dclock))) return bail(st);
   if ((st = dev_alloc(c, sizeof(uint32_t), (void**)&c->derr))) return bail(st);
-  if ((st = dev_alloc(c, 2 * sizeof(uint32_t), (void**)&c->dneq_count))) return bail(st);
-  if ((st = dev_alloc(c, (size_t)c->total_nodes * sizeof(uint2), (void**)&c->dneq_list))) return bail(st);
   if ((st = dev_alloc(c, 2 * (size_t)(n_instances + 1) * sizeof(uint32_t), (void**)&c->dbcount))) return bail(st);
   if (hipHostMalloc((void**)&c->herr, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
     fail(c, LBM_ERR_OOM, "hipHostMalloc failed");
     return bail(LBM_ERR_OOM);
   }
   *c->herr = 0;
-  if (hipEventCreateWithFlags(&c->err_event, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&c->err_event, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
     fail(c, LBM_ERR_DEVICE, "hipEventCreate failed");
     return bail(LBM_ERR_DEVICE);
   }
+  if (const char* e = std::getenv("KBC_SERIAL_BOUNDARY")) c->overlap = std::atoi(e) == 0;
   // Rest state: every deviation is zero in every storage format.
   if (hipMemsetAsync(c->buf[0], 0, off * c->esize, c->stream) != hipSuccess ||
       hipMemsetAsync(c->buf[1], 0, off * c->esize, c->stream) != hipSuccess ||
       hipMemsetAsync(c->flags, 0, foff, c->stream) != hipSuccess ||
       hipMemsetAsync(c->dclock, 0, sizeof(int64_t), c->stream) != hipSuccess ||
       hipMemsetAsync(c->derr, 0, sizeof(uint32_t), c->stream) != hipSuccess ||
-      hipMemsetAsync(c->dneq_count, 0, 2 * sizeof(uint32_t), c->stream) != hipSuccess ||
       hipMemsetAsync(c->dbcount, 0, 2 * (size_t)(n_instances + 1) * sizeof(uint32_t), c->stream) != hipSuccess) {
     fail(c, LBM_ERR_DEVICE, "hipMemsetAsync failed");
     return bail(LBM_ERR_DEVICE);
@@ -1290,24 +1340,17 @@ lbm_status lbm_step(lbm_ctx* c, int n_steps) {
   }
   lbm_status st;
   int n = n_steps;
-  // A step with source buffer k appends to counter k, which the previous
-  // step (source 1 - k) cleared.  If the source did not alternate (state
-  // restored by the host), clear both here, outside any captured graph.
-  if (n > 0 && c->last_src == c->cur)
-    HIPCHECK(c, hipMemsetAsync(c->dneq_count, 0, 2 * sizeof(uint32_t), c->stream));
   while (n > 0) {
     if (c->use_graph && n >= 2 && !c->graph_failed) {
       if ((st = ensure_graph(c, c->cur))) return st;
       if (c->graph[c->cur]) {
         HIPCHECK(c, hipGraphLaunch(c->graph[c->cur], c->stream));
-        c->last_src = 1 - c->cur;
         n -= 2;
         c->step += 2;
         continue;
       }
     }
     if ((st = enqueue_step(c, c->cur))) return st;
-    c->last_src = c->cur;
     c->cur ^= 1;
     c->step += 1;
     n -= 1;

@@ -988,18 +988,17 @@ __global__ void __launch_bounds__(BLOCK, WAVES)
           if (MEM & 1) __builtin_nontemporal_store(S::enc(f[i]), p); else *p = S::enc(f[i]);
         }
       }
-      // Near-equilibrium nodes go to the FP64 pass; one atomic per wave.
+      // Near-equilibrium nodes for the FP64 pass: each wave's 64 consecutive
+      // nodes have a mask word of their own, zero unless some node of theirs
+      // is deferred (the FP64 pass clears the words it finds set); the
+      // lowest deferred lane stores it with a plain store (a shared counter
+      // would take one same-address atomic per wave, which serialises when
+      // such nodes are spread over the domain).  Skipped lanes defer nothing.
       const uint64_t m = __ballot(co.fp64 != 0);
       if (m) {
-        const int lane = threadIdx.x & 63;
         const int leader = __ffsll((unsigned long long)m) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(b.neq_count, (uint32_t)__popcll(m));
-        base = __shfl(base, leader);
-        if (co.fp64) {
-          const uint32_t slot = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-          if (slot < b.neq_cap) b.neq_list[slot] = make_uint2((uint32_t)tl.inst, node[n]);
-        }
+        if ((int)(threadIdx.x & 63) == leader)
+          b.neq_words[(size_t)ti * b.neq_wpt + ((((uint32_t)k0 & ~63u) + (uint32_t)(n * BLOCK)) >> 6)] = m;
       }
       if (STATS && !co.fp64) {
         gmin = fminf(gmin, co.gamma);
@@ -1653,60 +1652,112 @@ __global__ void __launch_bounds__(256) k_neq_fixup(StepBuffers b, int stat0) {
   using T = typename S::T;
   using R = typename S::R;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    // End of the step: the next step appends to the other counter, which no
-    // kernel of this step reads; the boundary lists were consumed before;
-    // only the geometry and boundary kernels, which ran before, read the
-    // clock.
-    *b.neq_next = 0u;
+    // End of the step: the boundary lists were consumed before; only the
+    // geometry and boundary kernels, which ran before, read the clock.
     for (int j = 0; j < b.nbcount; ++j) b.bcount[j] = 0u;
     if (b.clock_tick) *b.clock_tick += 1;
   }
-  const uint32_t n = min(*b.neq_count, b.neq_cap);
   float gmin = 1e30f, gmax = -1e30f;
   double gsum = 0.0;
   uint32_t cnt = 0, f64 = 0;
-  for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
-    const uint2 e = b.neq_list[k];
-    const InstDev& I = b.insts[e.x];
-    const T* sb = static_cast<const T*>(b.src) + I.pop_off;
-    T* db = static_cast<T*>(b.dst) + I.pop_off;
-    const Coord c = node_coord(I, e.y);
-    R f[Q];
-    // Deferred nodes come from the bulk kernel, whose nodes have every source
-    // inside the instance (face planes and cut-link nodes are flagged and
-    // never deferred); a source that does not resolve means a corrupt list
-    // entry: the node is left as the bulk kernel wrote it and the error word
-    // is set.
-    bool resolved = true;
+  // Each wavefront takes 64 mask words at a time, one per lane, and works
+  // through their set bits 64 at a time: lane l takes the set bit of rank
+  // r + l in lane order, found from the exclusive prefix sum of the words'
+  // bit counts (the owner lane by binary search over lanes, then the bit
+  // within the owner's word by binary search over popcounts).
+  const int lane = threadIdx.x & 63;
+  const uint32_t nwaves = gridDim.x * 4u;
+  for (uint32_t c0 = (blockIdx.x * 4u + (threadIdx.x >> 6)) * 64u; c0 < b.neq_nwords;
+       c0 += nwaves * 64u) {
+    const uint32_t wi = c0 + (uint32_t)lane;
+    const uint64_t w = wi < b.neq_nwords ? b.neq_words[wi] : 0ull;
+    if (__ballot(w != 0ull) == 0ull) continue;
+    // Every word is zero again for the next step's bulk kernel.
+    if (w != 0ull) b.neq_words[wi] = 0ull;
+    const uint32_t pc = (uint32_t)__popcll(w);
+    uint32_t incl = pc;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      uint32_t m = e.y;
-      if (!resolve_nb(I, c.x, c.y, c.z, -cx(i), -cy(i), -cz<Q>(i), m)) {
-        resolved = false;
-        m = e.y;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t t = (uint32_t)__shfl_up((int)incl, d);
+      if (lane >= d) incl += t;
+    }
+    const uint32_t excl = incl - pc;
+    const uint32_t total = (uint32_t)__shfl((int)incl, 63);
+    for (uint32_t r = 0; r < total; r += 64u) {
+      const uint32_t g = r + (uint32_t)lane;
+      // Owner: the last lane o with excl[o] <= g (it has bits: a lane
+      // without bits shares its prefix with the lane after it).
+      int o = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        const int cand = o + step;
+        const uint32_t v = (uint32_t)__shfl((int)excl, cand & 63);
+        if (cand < 64 && v <= g) o = cand;
       }
-      f[i] = S::dec(sb[i * I.stride + m]);
-    }
-    if (!resolved) {
-      atomicOr(b.err, 2u);
-      continue;
-    }
-    CollideParams<R> P;
-    P.beta = (R)I.beta;
-    P.inv_beta = (R)(1.0 / I.beta);
-    P.beta_d = I.beta;
-    P.lbgk = I.collision;
-    P.trace_in_s = I.trace_in_s;
-    P.near_eq = I.near_eq;
-    CollideOut co;
-    if (!collide<Q, R, false>(f, P, co)) atomicOr(b.err, 1u);
+      const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)w, o);
+      const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(w >> 32), o);
+      uint64_t wo = ((uint64_t)hi << 32) | lo;
+      uint32_t rank = g - (uint32_t)__shfl((int)excl, o);
+      if (g >= total) continue;
+      int bit = 0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) db[i * I.stride + e.y] = S::enc(f[i]);
-    gmin = fminf(gmin, co.gamma);
-    gmax = fmaxf(gmax, co.gamma);
-    gsum += co.gamma;
-    cnt += 1;
-    f64 += 1;
+      for (int sh = 32; sh >= 1; sh >>= 1) {
+        const uint32_t cl = (uint32_t)__popcll(wo & ((1ull << sh) - 1ull));
+        if (rank >= cl) {
+          rank -= cl;
+          wo >>= sh;
+          bit += sh;
+        }
+      }
+      const uint32_t gw = c0 + (uint32_t)o;
+      const uint32_t ti = gw / b.neq_wpt;
+      const uint32_t loc = (gw - ti * b.neq_wpt) * 64u + (uint32_t)bit;
+      const Tile tl = b.tiles[ti];
+      // A bit beyond the tile's nodes names no node (the bulk kernel sets
+      // bits of its own nodes only): skipped.
+      if (loc >= (uint32_t)tl.count) continue;
+      const InstDev& I = b.insts[tl.inst];
+      const uint32_t node = (uint32_t)(tl.node0 + loc);
+      const T* sb = static_cast<const T*>(b.src) + I.pop_off;
+      T* db = static_cast<T*>(b.dst) + I.pop_off;
+      const Coord c = node_coord(I, node);
+      R f[Q];
+      // Deferred nodes come from the bulk kernel, whose nodes have every
+      // source inside the instance (face planes and cut-link nodes are
+      // flagged and never deferred); a source that does not resolve means a
+      // corrupt mask word: the node is left as the bulk kernel wrote it and
+      // the error word is set.
+      bool resolved = true;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        uint32_t m = node;
+        if (!resolve_nb(I, c.x, c.y, c.z, -cx(i), -cy(i), -cz<Q>(i), m)) {
+          resolved = false;
+          m = node;
+        }
+        f[i] = S::dec(sb[i * I.stride + m]);
+      }
+      if (!resolved) {
+        atomicOr(b.err, 2u);
+        continue;
+      }
+      CollideParams<R> P;
+      P.beta = (R)I.beta;
+      P.inv_beta = (R)(1.0 / I.beta);
+      P.beta_d = I.beta;
+      P.lbgk = I.collision;
+      P.trace_in_s = I.trace_in_s;
+      P.near_eq = I.near_eq;
+      CollideOut co;
+      if (!collide<Q, R, false>(f, P, co)) atomicOr(b.err, 1u);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) db[i * I.stride + node] = S::enc(f[i]);
+      gmin = fminf(gmin, co.gamma);
+      gmax = fmaxf(gmax, co.gamma);
+      gsum += co.gamma;
+      cnt += 1;
+      f64 += 1;
+    }
   }
   if (b.stats) block_stats<256>(gmin, gmax, gsum, cnt, f64, b.stats + stat0 + blockIdx.x);
 }

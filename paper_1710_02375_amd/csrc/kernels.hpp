@@ -30,10 +30,16 @@ struct StepBuffers {
   uint32_t* err;          // device error word
   const int64_t* clock;   // steps taken before this step
   StatPartial* stats;     // per-workgroup statistics, or null
-  uint32_t* neq_count;    // near-equilibrium nodes deferred to the FP64 pass
-  uint2* neq_list;        // (instance, node) of each deferred node
-  uint32_t neq_cap;
-  uint32_t* neq_next;     // the next step's counter, cleared by the FP64 pass
+  // Near-equilibrium nodes deferred to the FP64 pass: one 64-bit mask per
+  // 64 consecutive nodes of a tile, word ti * neq_wpt + j for nodes
+  // [64 j, 64 j + 64) of tile ti (neq_wpt = tile size / 64), bit l for the
+  // node 64 j + l.  Every word is zero at the start of a step; the bulk
+  // kernel stores the words with a deferred node, and the FP64 pass reads
+  // neq_nwords words (none in the multiphase pipeline) and clears those set.
+  uint64_t* neq_words;
+  uint32_t neq_nwords;
+  uint32_t neq_wpt;
+  const Tile* tiles;      // the tile table the bulk kernel ran over
   int64_t* clock_tick;    // advanced by one at the end of the step, or null
   uint32_t* bcount;       // boundary-list counters, cleared by the FP64 pass
   int nbcount;
@@ -82,9 +88,9 @@ struct Ops {
                         const uint8_t* flags, double* rho, double* u, double* partials,
                         int* nparts, hipStream_t s);
   // Redoes the deferred near-equilibrium nodes with the FP64 gamma (grid of
-  // nblocks workgroups striding over the list); statistics go to
-  // stats[stat0 + workgroup].  It also ends the step: clears neq_next and
-  // advances clock_tick.
+  // nblocks workgroups striding over the mask words); statistics go to
+  // stats[stat0 + workgroup].  It also ends the step: clears the boundary
+  // list counters and advances clock_tick.
   hipError_t (*fixup)(const StepBuffers& b, int nblocks, int stat0, hipStream_t s);
   // Wall force (per point traction, per-workgroup partial force sums: four
   // doubles per workgroup, force_points_per_workgroup(Q) points each).

@@ -220,6 +220,82 @@ def test_fp64_gamma_pass_runs_and_matches_oracle(storage, monkeypatch):
     s.close()
 
 
+@pytest.mark.parametrize("Q,dims", [(27, [(19, 13, 11), (9, 7, 5), (17, 3, 4)]),
+                                    (9, [(37, 23, 1), (9, 7, 1), (71, 3, 1)])])
+def test_fp64_gamma_pass_partial_batched_every_variant(Q, dims, monkeypatch):
+    """Deferred nodes spread over a batch: three FP32 instances of ragged
+    sizes in one launch, each in a uniform flow with a quiet half (velocity
+    perturbation 1e-6: <Delta|Delta> far below the threshold times the
+    squared deviation from rest, deferred to the FP64-gamma pass) and a
+    perturbed half (0.05: not deferred).  For every bulk variant (tiles of 128
+    to 1024 nodes, so the per-tile mask words end on partial tiles of every
+    instance) each instance also runs alone: there the statistics give a
+    share of FP64-gamma nodes well inside (0, 1) after one step, and the
+    batch must reproduce each lone instance bitwise (a deferred node whose
+    mask bit were lost or misplaced would keep its FP32 gamma) and match the
+    FP64 oracle after 1 and 6 steps; all variants agree bitwise."""
+    from paper_1710_02375_amd import lbm
+
+    monkeypatch.setenv("KBC_NEAR_EQ", "1e-5")
+    D = 3 if Q == 27 else 2
+    rng = np.random.default_rng(7)
+    fields = []
+    for nx, ny, nz in dims:
+        N = nx * ny * nz
+        x = np.arange(N) % nx
+        amp = np.where(x < nx // 2, 1e-6, 0.05)
+        u0 = np.array([0.05, 0.02, -0.03][:D])[:, None]
+        fields.append((1.0 + 0.01 * amp * rng.standard_normal(N),
+                       u0 + amp * rng.standard_normal((D, N))))
+    w = lattice_w(Q)[:, None]
+    refs = {}
+    for k, ((nx, ny, nz), (rho, u)) in enumerate(zip(dims, fields)):
+        d = oracle.Domain(Q, nx, ny, nz, 0.02)
+        d.init_fields(rho, u)
+        for steps in (1, 5):
+            d.step(steps)
+            refs[(k, d.time)] = d.get_populations()
+    say("case: partial FP64-gamma pass, Q=%d batch of %s, every variant" % (Q, dims))
+
+    def run(descs, flds, v):
+        s = lbm.Solver(descs)
+        s.set_stats(True)
+        for k, (rho, u) in enumerate(flds):
+            s.init_fields(rho, u, inst=k)
+        lbm.lbm_set_variant(s.ctx, v)
+        out = []
+        for steps in (1, 5):
+            s.step(steps)
+            shares = [s.moments(inst=k, fields=False)[2]["fp64_gamma_fraction"]
+                      for k in range(len(descs))]
+            out.append(([s.get_populations(k) for k in range(len(descs))], shares))
+        s.close()
+        return out
+
+    descs = [dict(Q=Q, nx=nx, ny=ny, nz=nz, nu=0.02, storage="f32") for nx, ny, nz in dims]
+    finals = None
+    for v in range(lbm.lbm_variant_count()):
+        name = lbm.lbm_variant_name(v)
+        batch = run(descs, fields, v)
+        alone = [run([dsc], [fld], v) for dsc, fld in zip(descs, fields)]
+        errs, shares = [], []
+        for j, t in enumerate((1, 6)):
+            for k in range(len(dims)):
+                f = batch[j][0][k]
+                assert np.array_equal(f, alone[k][j][0][0]), (name, t, k)
+                errs.append(float(np.max(np.abs(f - refs[(k, t)]) / w)))
+                if t == 1:   # later the perturbation has spread over the quiet half
+                    shares.append(alone[k][j][1][0])
+            assert max(errs) < (1e-6 if t == 1 else 1e-5), (name, t, errs)
+        assert all(0.2 < sh < 0.8 for sh in shares), (name, shares)
+        state = batch[1][0]
+        if finals is None:
+            finals = state
+            say("  %s: fp64 shares alone %s, max |df|/W_i %.2e" % (name, ["%.3f" % x for x in shares], max(errs)))
+        else:
+            assert all(np.array_equal(a, b) for a, b in zip(finals, state)), name
+
+
 def test_cfg1_tg2d_64_f64_analytic_and_oracle():
     """D2Q9 KBC Taylor-Green 64x64, FP64, u0=0.02, nu=0.01, 500 steps."""
     n, nu, steps = 64, 0.01, 500
