@@ -233,7 +233,7 @@ def sphere_form(lbm, torch, storage, steps, sample_every, variant=None, dims=(51
         names = [lbm.lbm_variant_name(k) for k in range(lbm.lbm_variant_count())]
         lbm.lbm_set_variant(s.ctx, names.index(variant))
     else:
-        lbm.lbm_autotune(s.ctx, os.environ.get("KBC_AUTOTUNE_CACHE"))
+        variant = lbm.lbm_variant_name(lbm.lbm_autotune(s.ctx, os.environ.get("KBC_AUTOTUNE_CACHE")))
     U, R = cfg["U"], cfg["radius"]
     norm = 0.5 * U * U * math.pi * R * R
     series = []
@@ -261,6 +261,7 @@ def sphere_form(lbm, torch, storage, steps, sample_every, variant=None, dims=(51
     s.close()
     # The first call allocates the persistent workspace; report the median.
     return {"MLUPS": round(N * steps / t_step / 1e6, 1), "ms_per_step": round(t_step * 1e3 / steps, 5),
+            "variant": variant,
             "series": series, "u": uu, "mass": tot["mass"],
             "wall_force_ms_5120_points": round(1e3 * float(np.median(t_force)), 4),
             "wall_force_noalloc_ms_5120_points": round(1e3 * float(np.median(t_force_na)), 4)}

@@ -1126,9 +1126,11 @@ __global__ void __launch_bounds__(256) k_boundary_scan(const InstDev* __restrict
 // storage form, as for the other boundary nodes.  Consecutive list entries
 // are mostly consecutive nodes of a wall row, so the loads coalesce.
 template <int Q, int ST, bool PRE>
-__global__ void __launch_bounds__(64) k_boundary_wall(StepBuffers b, const uint2* __restrict__ list,
-                                                     const uint32_t* __restrict__ count,
-                                                     uint32_t cap, int stat0) {
+__device__ __forceinline__ void boundary_wall_nodes(const StepBuffers& b,
+                                                    const uint2* __restrict__ list,
+                                                    const uint32_t* __restrict__ count,
+                                                    uint32_t cap, int stat_slot, uint32_t bid,
+                                                    uint32_t nblk) {
   using S = Store<ST>;
   using T = typename S::T;
   const double t1 = (double)(*b.clock + 1);
@@ -1136,7 +1138,7 @@ __global__ void __launch_bounds__(64) k_boundary_wall(StepBuffers b, const uint2
   double gsum = 0.0;
   uint32_t cnt = 0, f64 = 0;
   const uint32_t n = min(*count, cap);
-  for (uint32_t k = blockIdx.x * 64 + threadIdx.x; k < n; k += gridDim.x * 64) {
+  for (uint32_t k = bid * 64 + threadIdx.x; k < n; k += nblk * 64) {
     const uint2 e = list[k];
     const InstDev& I = b.insts[e.x];
     const T* sb = static_cast<const T*>(b.src) + I.pop_off;
@@ -1176,7 +1178,15 @@ __global__ void __launch_bounds__(64) k_boundary_wall(StepBuffers b, const uint2
     cnt += 1;
     f64 += 1;
   }
-  if (b.stats) block_stats<64>(gmin, gmax, gsum, cnt, f64, b.stats + stat0 + blockIdx.x);
+  if (b.stats) block_stats<64>(gmin, gmax, gsum, cnt, f64, b.stats + stat_slot);
+}
+
+template <int Q, int ST, bool PRE>
+__global__ void __launch_bounds__(64) k_boundary_wall(StepBuffers b, const uint2* __restrict__ list,
+                                                     const uint32_t* __restrict__ count,
+                                                     uint32_t cap, int stat0) {
+  boundary_wall_nodes<Q, ST, PRE>(b, list, count, cap, stat0 + (int)blockIdx.x, blockIdx.x,
+                                  gridDim.x);
 }
 
 // One DPP lane exchange of a double (two 32-bit moves); CTRL is the DPP
@@ -1249,9 +1259,11 @@ __device__ __forceinline__ int lag_slot(int i, int k) {
 // Workgroups (one wavefront) stride over the node list.
 // ---------------------------------------------------------------------------
 template <int Q, int ST, bool PRE>
-__global__ void __launch_bounds__(64) k_boundary_wave(StepBuffers b, const uint2* __restrict__ list,
-                                                     const uint32_t* __restrict__ count,
-                                                     uint32_t cap, int stat0) {
+__device__ __forceinline__ void boundary_wave_nodes(const StepBuffers& b,
+                                                    const uint2* __restrict__ list,
+                                                    const uint32_t* __restrict__ count,
+                                                    uint32_t cap, int stat_slot, uint32_t bid,
+                                                    uint32_t nblk) {
   using S = Store<ST>;
   using T = typename S::T;
   constexpr int D = dims<Q>();
@@ -1270,7 +1282,7 @@ __global__ void __launch_bounds__(64) k_boundary_wave(StepBuffers b, const uint2
   double gsum = 0.0;
   uint32_t cnt = 0, f64 = 0;
   const uint32_t n = min(*count, cap);
-  for (uint32_t base = blockIdx.x * NG; base < n; base += gridDim.x * NG) {
+  for (uint32_t base = bid * NG; base < n; base += nblk * NG) {
     const uint32_t k = base + g;
     const bool active = k < n;
     const uint2 e = active ? list[k] : make_uint2(0u, 0u);
@@ -1567,7 +1579,30 @@ __global__ void __launch_bounds__(64) k_boundary_wave(StepBuffers b, const uint2
     }
     __syncthreads();
   }
-  if (b.stats) block_stats<64>(gmin, gmax, gsum, cnt, f64, b.stats + stat0 + blockIdx.x);
+  if (b.stats) block_stats<64>(gmin, gmax, gsum, cnt, f64, b.stats + stat_slot);
+}
+
+template <int Q, int ST, bool PRE>
+__global__ void __launch_bounds__(64) k_boundary_wave(StepBuffers b, const uint2* __restrict__ list,
+                                                     const uint32_t* __restrict__ count,
+                                                     uint32_t cap, int stat0) {
+  boundary_wave_nodes<Q, ST, PRE>(b, list, count, cap, stat0 + (int)blockIdx.x, blockIdx.x,
+                                  gridDim.x);
+}
+
+// Both node lists in one launch: workgroups [0, nwg) take the cut-link nodes
+// one wavefront (group) at a time, the rest the wall-row nodes one thread
+// each, so the two run side by side rather than one after the other.  Used
+// where the two kernels have the same register budget (D2Q9).
+template <int Q, int ST, bool PRE>
+__global__ void __launch_bounds__(64) k_boundary_both(StepBuffers b, const uint2* __restrict__ list,
+                                                     const uint32_t* __restrict__ count,
+                                                     uint32_t cap, int stat0, uint32_t nwg) {
+  if (blockIdx.x < nwg)
+    boundary_wave_nodes<Q, ST, PRE>(b, list, count, cap, stat0 + (int)blockIdx.x, blockIdx.x, nwg);
+  else
+    boundary_wall_nodes<Q, ST, PRE>(b, list + cap, count + 1, cap, stat0 + (int)blockIdx.x,
+                                    blockIdx.x - nwg, gridDim.x - nwg);
 }
 
 // ---------------------------------------------------------------------------
@@ -2377,6 +2412,15 @@ static hipError_t launch_boundary(const StepBuffers& b, const Region* regions,
   if (nbt <= 0 || (nwg <= 0 && nwall <= 0)) return hipSuccess;
   hipLaunchKernelGGL((k_boundary_scan<Q>), dim3(nbt), dim3(256), 0, s, b.insts, regions, btiles,
                      bt0, b.flags, list, cap, count);
+  if (Q == 9 && nwg > 0 && nwall > 0) {
+    if (pre)
+      hipLaunchKernelGGL((k_boundary_both<Q, ST, true>), dim3(nwg + nwall), dim3(64), 0, s, b, list,
+                         count, cap, stat0, (uint32_t)nwg);
+    else
+      hipLaunchKernelGGL((k_boundary_both<Q, ST, false>), dim3(nwg + nwall), dim3(64), 0, s, b,
+                         list, count, cap, stat0, (uint32_t)nwg);
+    return hipGetLastError();
+  }
   if (nwg > 0) {
     if (pre)
       hipLaunchKernelGGL((k_boundary_wave<Q, ST, true>), dim3(nwg), dim3(64), 0, s, b, list,
