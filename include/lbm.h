@@ -178,7 +178,11 @@ lbm_status lbm_set_geometry(lbm_ctx* ctx, int inst, const lbm_body* body);
 
 /* Advances every instance by n_steps >= 0 steps (Sec. II.A, Eq. 1, pull form:
  * geometry update, fresh-node refill, streaming, Grad fill, face conditions,
- * KBC collision).  Asynchronous on the context stream.  Each call that
+ * KBC collision).  Asynchronous on the context stream: with boundary nodes
+ * the boundary kernels of a step run on a private side stream of the
+ * context that forks from the context stream after the geometry update and
+ * joins it again before the step ends, so work enqueued on the context
+ * stream afterwards sees the whole step.  Each call that
  * enqueues steps also enqueues a copy of the device error word to the host
  * and records an event after it; the next lbm_step call checks that copy if
  * the event has completed (without waiting for it) and returns
