@@ -137,6 +137,33 @@ def test_moving_sphere_parity_with_fresh_nodes(storage, tol):
     assert Fg[0] < 0
 
 
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_boundary_side_stream_equals_serial(use_graph, monkeypatch):
+    """The boundary kernels run on a side stream beside the bulk kernel.  An
+    oscillating sphere in a D3Q27 FP32 channel with inflow, outflow and four
+    walls (cut-link wavefronts, wall rows, face planes, fresh nodes) must
+    reach bitwise the state of the all-serial launch sequence, with graph
+    replay and with one launch sequence per step."""
+    from paper_1710_02375_amd import lbm
+
+    nx, ny, nz = 48, 20, 18
+    faces = ["inlet", "outlet", "wall", "wall", "wall", "wall"]
+    say("case: side stream vs serial, sphere channel %dx%dx%d, graph %s" % (nx, ny, nz, use_graph))
+    outs = []
+    for serial in ("1", "0"):
+        monkeypatch.setenv("KBC_SERIAL_BOUNDARY", serial)
+        s = lbm.Solver([dict(Q=27, nx=nx, ny=ny, nz=nz, nu=0.04, storage="f32", faces=faces,
+                             u_in=(0.04, 0.0, 0.0), ramp_steps=10)], use_graph=use_graph)
+        N = nx * ny * nz
+        s.init_fields(np.ones(N), np.zeros((3, N)))
+        s.set_body(W.BODY_SPHERE, W.sphere_params((16.3, 10.1, 8.8), 4.0, (2.0, 0.5, 0), 120.0))
+        s.step(31)
+        outs.append(s.get_populations())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+    assert np.abs(outs[1] - outs[1][:, :1]).max() > 1e-3   # the flow did develop
+
+
 def test_flap_channel_parity_f64():
     ch = W.flap_channels(count=1, seed=2375)[0]
     nx, ny = 96, 48
