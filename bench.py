@@ -239,6 +239,7 @@ def sphere_form(lbm, torch, storage, steps, sample_every, variant=None, dims=(51
     series = []
     t_force, t_force_na = [], []
     t_step = 0.0
+    chunks = []   # (first step, steps, seconds) of each timed chunk
     done = 0
     while done < steps:
         k = min(sample_every, steps - done)
@@ -246,7 +247,9 @@ def sphere_form(lbm, torch, storage, steps, sample_every, variant=None, dims=(51
         t0 = time.perf_counter()
         s.step(k)
         stream.synchronize()
-        t_step += time.perf_counter() - t0
+        el = time.perf_counter() - t0
+        t_step += el
+        chunks.append((done, k, el))
         done += k
         c = p[0:3] + p[4:7] * math.sin(p[7] * done + p[8])
         xq, nq, wq = W.sphere_quadrature(c, R, subdiv=4)
@@ -260,7 +263,12 @@ def sphere_form(lbm, torch, storage, steps, sample_every, variant=None, dims=(51
     _, uu, tot = s.moments()
     s.close()
     # The first call allocates the persistent workspace; report the median.
+    # The rate once the inflow ramp is over (the chunks from its end on).
+    after = [(k, el) for d0, k, el in chunks if d0 >= cfg["ramp_steps"]]
+    after_ramp = (round(N * sum(k for k, _ in after) / sum(el for _, el in after) / 1e6, 1)
+                  if after else None)
     return {"MLUPS": round(N * steps / t_step / 1e6, 1), "ms_per_step": round(t_step * 1e3 / steps, 5),
+            "MLUPS_after_ramp": after_ramp, "ramp_steps": cfg["ramp_steps"],
             "variant": variant,
             "series": series, "u": uu, "mass": tot["mass"],
             "wall_force_ms_5120_points": round(1e3 * float(np.median(t_force)), 4),
@@ -278,6 +286,8 @@ def sphere_workload(lbm, torch, args, forms=("f64", "f32", "f16")):
         if ref is None:
             ref = r
         entry = {"MLUPS": r["MLUPS"], "ms_per_step": r["ms_per_step"],
+                 "MLUPS_after_ramp": r["MLUPS_after_ramp"], "ramp_steps": r["ramp_steps"],
+                 "variant": r["variant"],
                  "wall_force_ms_5120_points": r["wall_force_ms_5120_points"],
                  "wall_force_noalloc_ms_5120_points": r["wall_force_noalloc_ms_5120_points"],
                  "Cd_Cl_last": [round(v, 6) for v in r["series"][-1][1:3]]}
