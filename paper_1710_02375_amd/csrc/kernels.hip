@@ -1122,9 +1122,18 @@ __global__ void __launch_bounds__(256) k_boundary_scan(const InstDev* __restrict
 // Nodes whose missing populations all come from wall faces (resting walls
 // half a spacing outside the face, q = 1/2), one thread each: the
 // pre-collision state with Grad's approximation for the missing populations
-// (Sec. II.C.1) and the KBC collision (Eqs. 1-6), both in FP64 whatever the
-// storage form, as for the other boundary nodes.  Consecutive list entries
+// (Sec. II.C.1) and the KBC collision (Eqs. 1-6), in FP64 except for D3Q27
+// with FP32 or 16-bit storage (see RW below).  Consecutive list entries
 // are mostly consecutive nodes of a wall row, so the loads coalesce.
+template <bool C, typename A, typename B>
+struct pick_type {
+  using type = A;
+};
+template <typename A, typename B>
+struct pick_type<false, A, B> {
+  using type = B;
+};
+
 template <int Q, int ST, bool PRE>
 __device__ __forceinline__ void boundary_wall_nodes(const StepBuffers& b,
                                                     const uint2* __restrict__ list,
@@ -1133,6 +1142,13 @@ __device__ __forceinline__ void boundary_wall_nodes(const StepBuffers& b,
                                                     uint32_t nblk) {
   using S = Store<ST>;
   using T = typename S::T;
+  // Arithmetic type: the storage's (FP32 for FP32 and 16-bit storage, with
+  // gamma from FP64 near equilibrium, as in the bulk kernel) for D3Q27
+  // collisions, whose FP64 form needs 256 VGPRs and spills (one wave per
+  // SIMD); FP64 for D2Q9 (its launch is shared with the cut-link kernel,
+  // whose registers bound it anyway) and for the multiphase pre-collision
+  // state.
+  using RW = typename pick_type<(Q == 27 && !PRE), typename S::R, double>::type;
   const double t1 = (double)(*b.clock + 1);
   float gmin = 1e30f, gmax = -1e30f;
   double gsum = 0.0;
@@ -1145,10 +1161,10 @@ __device__ __forceinline__ void boundary_wall_nodes(const StepBuffers& b,
     T* db = static_cast<T*>(b.dst) + I.pop_off;
     const uint8_t* fl = b.flags + I.flag_off;
     const Coord c = node_coord(I, e.y);
-    double f[Q];
+    RW f[Q];
     // Every missing population of these nodes comes from a wall face (q = 1/2,
     // at rest): the body cut-link code is left out.
-    gather_pre<Q, ST, double, true, PRE>(I, sb, fl, c.x, c.y, c.z, t1, f);
+    gather_pre<Q, ST, RW, true, PRE>(I, sb, fl, c.x, c.y, c.z, t1, f);
     if constexpr (PRE) {
       // Multiphase: the pre-collision state and its density, for the forced
       // collision that follows.
@@ -1161,22 +1177,25 @@ __device__ __forceinline__ void boundary_wall_nodes(const StepBuffers& b,
       mp_put<ST>(I, e.y, 1.0 + rt);
       continue;
     }
-    CollideParams<double> P;
-    P.beta = I.beta;
-    P.inv_beta = 1.0 / I.beta;
+    CollideParams<RW> P;
+    P.beta = (RW)I.beta;
+    P.inv_beta = (RW)(1.0 / I.beta);
     P.beta_d = I.beta;
     P.lbgk = I.collision;
     P.trace_in_s = I.trace_in_s;
-    P.near_eq = 0.0f;
+    P.near_eq = sizeof(RW) == 4 ? I.near_eq : 0.0f;
     CollideOut co;
-    if (!collide<Q, double, false>(f, P, co)) atomicOr(b.err, 1u);
+    if (!collide<Q, RW, false>(f, P, co)) atomicOr(b.err, 1u);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) db[i * I.stride + e.y] = S::enc_d(f[i]);
+    for (int i = 0; i < Q; ++i) {
+      if constexpr (sizeof(RW) == 4) db[i * I.stride + e.y] = S::enc(f[i]);
+      else db[i * I.stride + e.y] = S::enc_d(f[i]);
+    }
     gmin = fminf(gmin, co.gamma);
     gmax = fmaxf(gmax, co.gamma);
     gsum += co.gamma;
     cnt += 1;
-    f64 += 1;
+    f64 += sizeof(RW) == 4 ? (uint32_t)co.fp64 : 1u;
   }
   if (b.stats) block_stats<64>(gmin, gmax, gsum, cnt, f64, b.stats + stat_slot);
 }
@@ -1255,7 +1274,7 @@ __device__ __forceinline__ int lag_slot(int i, int k) {
 //   lane i < Q            f*_i for the missing i, then the KBC collision
 //                         (Eqs. 1-6) lane-parallel in FP64 with group sums,
 //                         and the store of population i.
-// The arithmetic of the boundary nodes is FP64 for every storage form.
+// The arithmetic of the cut-link nodes is FP64 for every storage form.
 // Workgroups (one wavefront) stride over the node list.
 // ---------------------------------------------------------------------------
 template <int Q, int ST, bool PRE>
