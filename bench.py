@@ -305,6 +305,36 @@ def sphere_workload(lbm, torch, args, forms=("f64", "f32", "f16")):
             "forms": out}
 
 
+def channel3d_workload(lbm, torch, steps=200, warmup=300, dims=(512, 128, 128)):
+    """D3Q27 FP32 channel without a body, three face sets: periodic, four
+    walls (wall-row nodes on the y and z faces), four walls with inflow and
+    outflow; MLUPS of each, to show the cost of the wall rows."""
+    nx, ny, nz = dims
+    N = nx * ny * nz
+    cases = {"periodic": ["periodic"] * 6,
+             "walls": ["periodic", "periodic", "wall", "wall", "wall", "wall"],
+             "walls_inflow_outflow": ["inlet", "outlet", "wall", "wall", "wall", "wall"]}
+    out = {}
+    for name, faces in cases.items():
+        stream = torch.cuda.Stream()
+        s = lbm.Solver([dict(Q=27, nx=nx, ny=ny, nz=nz, nu=0.01, storage="f32", faces=faces,
+                             u_in=(0.05, 0.0, 0.0), ramp_steps=0)], stream=stream)
+        s.init_fields(np.ones(N), np.zeros((3, N)))
+        v = lbm.lbm_autotune(s.ctx, os.environ.get("KBC_AUTOTUNE_CACHE"))
+        s.step(warmup)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        stream.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"MLUPS": round(N * steps / el / 1e6, 1), "ms_per_step": round(el * 1e3 / steps, 5),
+                     "variant": lbm.lbm_variant_name(v)}
+        s.close()
+    return {"metric": "MLUPS by face set", "unit": "MLUPS",
+            "config": {"workload": "D3Q27 KBC channel %dx%dx%d, FP32, no body, inflow 0.05" % dims},
+            "forms": out}
+
+
 def multiphase_form(lbm, torch, storage, steps, warmup, dims=(320, 250, 320), kappa=0.025,
                     kappa_w=-0.145, nu=0.05):
     """Droplet of diameter 80 hitting a non-wetting wall (Sec. III.B
@@ -537,7 +567,8 @@ def main():
     ap.add_argument("--fsi-seconds", type=float, default=8.0)
     ap.add_argument("--fsi-window", type=float, default=2.0)
     ap.add_argument("--workload", default="tg256",
-                    choices=["tg256", "tg512", "sphere", "batched", "multiphase", "fsi3"],
+                    choices=["tg256", "tg512", "sphere", "batched", "multiphase", "fsi3",
+                             "channel3d"],
                     help="tg256 is the headline line; the others print their own line")
     ap.add_argument("--sphere-steps", type=int, default=1200)
     ap.add_argument("--sphere-sample", type=int, default=200)
@@ -570,6 +601,9 @@ def main():
         return
     if args.workload == "fsi3":
         print(json.dumps(fsi3_workload(lbm, torch, args)), flush=True)
+        return
+    if args.workload == "channel3d":
+        print(json.dumps(channel3d_workload(lbm, torch)), flush=True)
         return
     if args.workload == "multiphase":
         print(json.dumps(multiphase_workload(lbm, torch, args)), flush=True)
